@@ -1,0 +1,167 @@
+/*
+ * dg.h - C ABI of the MI355X (gfx950) elastic ADER-DG element-kernel library.
+ *
+ * The library evaluates the element-local kernels of an ADER-DG scheme for
+ * the linear elastic wave equation on unstructured tetrahedral meshes, as
+ * written in Uphoff & Bader, "Yet Another Tensor Toolbox for discontinuous
+ * Galerkin methods and other applications", Sec. 5.1.1:
+ *   - the Cauchy-Kowalevski predictor        (Eq. seissol:derivative)
+ *   - the Taylor time integral               (Eq. seissol:timeint)
+ *   - the volume and local flux terms        (Eq. seissol:correction_local)
+ *   - the neighbour flux term                (Eq. seissol:correction_neigh)
+ *
+ * Conventions
+ *   degree N in 2..6;  B = (N+1)(N+2)(N+3)/6 volume and Bf = (N+1)(N+2)/2
+ *   face basis functions (Sec. 5.1.1); 9 quantities in the order
+ *   s_xx s_yy s_zz s_xy s_yz s_xz u v w (velocity-stress form of Eq.
+ *   linearpde).  Basis: Dubiner's functions on the reference tetrahedron
+ *   (0,0,0),(1,0,0),(0,1,0),(0,0,1) in the collapsed-coordinate Jacobi form,
+ *   ordered by total degree, then by the zeta index, then by the eta index.
+ *   Local face s of an element is the local-vertex triple (0,2,1), (0,1,3),
+ *   (0,3,2), (1,2,3) with outward normal (x_b-x_a)x(x_c-x_a).
+ *
+ *   All DOF-like arrays are element major, basis index fastest:
+ *     Q, I      [E][9][B]          DOFs, time integral
+ *     T         [E][N+1][9][B]     Taylor-scaled time derivatives
+ *                                  T^d = dt^d/d! * D^d  (rows of T^d at or
+ *                                  beyond C(N-d+3,3) are written as 0)
+ *     traces    [E][4][9][Bf]      face traces R^s^T I of every element
+ *     star_packed [E][9][3][3]     star matrices in packed form (see
+ *                                  dg_pack_star), element type of the plan
+ *     Aplus, Aminus [E][4][9][9]   flux-solver matrices, FP64, row major
+ *                                  (row = output quantity), geometric factor
+ *                                  -2|S|/det J and rotation folded in
+ *     neigh     [E][4] int32       neighbour element of each face (-1: none;
+ *                                  then that face's neighbour term is 0)
+ *     face_rot  [E][4] uint8       j | h << 2: the neighbour's local face j
+ *                                  and the orientation h (position of this
+ *                                  face's first vertex in the neighbour's
+ *                                  face triple)
+ *   The element type of DOF arrays is double for DG_FP64 plans and float for
+ *   DG_FP32 plans.
+ *
+ * Memory and streams: every array argument of the dg_* compute calls is a
+ * DEVICE pointer owned by the caller; the library does not allocate, free or
+ * retain caller memory.  Calls are enqueued on the caller's hipStream_t and
+ * return before the GPU work completes.  Host-side helpers (suffix _host and
+ * dg_reference_matrices) take host pointers and run synchronously.
+ *
+ * Errors: every call returns a dg_status.  Argument errors (null pointer,
+ * negative size, unsupported degree or precision, misaligned pointer) are
+ * reported synchronously and nothing is enqueued.  A failed kernel launch
+ * returns DG_EHIP; faults during execution surface from dg_sync.  The text
+ * of the last error of the calling thread is available from dg_last_error.
+ * Plans are immutable after creation and may be shared between threads.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_plan dg_plan;
+
+typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
+
+typedef enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,
+    DG_EUNSUPPORTED = -2,
+    DG_EHIP = -3,
+    DG_ENOMEM = -4
+} dg_status;
+
+/* ---- host helpers ------------------------------------------------------ */
+
+/* Number of doubles written by dg_reference_matrices for `degree`. */
+int64_t dg_reference_blob_size(int degree);
+
+/* Reference matrices of Sec. 5.1.1 for `degree` (host, FP64, row major),
+ * concatenated: Khat[3][B][B], Ktilde[3][B][B], R[4][B][Bf], Rhat[4][B][Bf],
+ * f[3][Bf][Bf], mass[B], face_mass[Bf].  Khat^d = M^-1 S^d and
+ * Ktilde^d = -M^-1 S^d^T with S^d_kl = int dphi_k/dxi_d phi_l; R^s_ln is the
+ * face-basis projection of phi_l on face s, Rhat^s = M^-1 R^s Mf, f^h maps
+ * face coefficients between the two orientations of a shared face.
+ * `out` must hold dg_reference_blob_size(degree) doubles. */
+int dg_reference_matrices(int degree, double *out);
+
+/* Star matrices and flux solvers of every element (host, FP64).
+ * X [E][4][3] vertex coordinates, materials [E][3] = (rho, cp, cs),
+ * neigh [E][4].  Writes star [E][3][9][9] (A*^d = sum_j dxi_d/dx_j A^(j),
+ * Sec. 5.1.1), Aplus and Aminus [E][4][9][9] (exact Godunov flux between the
+ * element's and the neighbour's isotropic materials).  Host pointers. */
+int dg_element_data_host(int64_t E, const double *X, const double *materials, const int32_t *neigh,
+                         double *star, double *Aplus, double *Aminus);
+
+/* ---- plans ------------------------------------------------------------- */
+
+int dg_plan_create(int degree, dg_precision precision, dg_plan **out);
+int dg_plan_destroy(dg_plan *plan);
+/* B and Bf of a plan (either pointer may be NULL). */
+int dg_plan_sizes(const dg_plan *plan, int *B, int *Bf);
+const char *dg_last_error(void);
+
+/* ---- device compute calls (stream ordered) ----------------------------- */
+
+/* Packs dense FP64 star matrices [E][3][9][9] into the plan's packed form
+ * [E][9][3][3]: entry [p][d][i] is star^d[p][q_i(p)] with the elastic
+ * coupling columns q(p) = (6,7,8) for p<3, (6,7,-) p=3, (7,8,-) p=4,
+ * (6,8,-) p=5, (0,3,5) p=6, (1,3,4) p=7, (2,4,5) p=8 ('-' stored as 0).
+ * Entries of the dense matrices outside this pattern are ignored. */
+int dg_pack_star(const dg_plan *plan, int64_t E, const double *star_dense, void *star_packed,
+                 hipStream_t stream);
+
+/* Eq. seissol:derivative: T[e][d] = dt^d/d! D^d for d = 0..N, D^0 = Q. */
+int dg_predictor(const dg_plan *plan, int64_t E, double dt, const void *Q, const void *star_packed,
+                 void *T, hipStream_t stream);
+
+/* Eq. seissol:timeint: I = sum_d dt/(d+1) T^d, accumulated in FP64. */
+int dg_time_integral(const dg_plan *plan, int64_t E, double dt, const void *T, void *I,
+                     hipStream_t stream);
+
+/* Eq. seissol:correction_local, stiffness part: Q += sum_d Khat^d I star^d^T. */
+int dg_volume(const dg_plan *plan, int64_t E, const void *I, const void *star_packed, void *Q,
+              hipStream_t stream);
+
+/* Eq. seissol:correction_local, face part: Q += sum_s Rhat^s (R^s^T I) Aplus^s^T. */
+int dg_local_flux(const dg_plan *plan, int64_t E, const void *I, const double *Aplus, void *Q,
+                  hipStream_t stream);
+
+/* Eq. seissol:correction_neigh:
+ * Q += sum_s Rhat^s f^h (R^j^T I[neigh]) Aminus^s^T, (j,h) from face_rot.
+ * I [n_I][9][B] holds the time integrals of the elements neigh refers to;
+ * neighbour indices outside [0, n_I) are treated like -1 (no neighbour). */
+int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I, const int32_t *neigh,
+                      const uint8_t *face_rot, const double *Aminus, void *Q, hipStream_t stream);
+
+/* n_steps global time steps of the full scheme (predictor, time integral,
+ * volume, local and neighbour flux) on all E elements, Q updated in place.
+ * I [E][9][B] and traces [E][4][9][Bf] are caller-provided work arrays; on
+ * return they hold the time integral and face traces of the last step.
+ * Neighbour indices must lie in [0, E); others are treated like -1. */
+int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
+            const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
+            const uint8_t *face_rot, hipStream_t stream);
+
+/* The two launches of one dg_step, exposed separately so that a caller can
+ * place work (for instance an exchange of partition-boundary traces) between
+ * them.  dg_step_predict: I = time integral of the predictor of Q and
+ * traces[e][s] = R^s^T I[e].  dg_step_correct: Q += volume + local flux +
+ * neighbour flux, the local and neighbour terms read from `traces`. */
+int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, const void *star_packed,
+                    void *I, void *traces, hipStream_t stream);
+int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *traces,
+                    const void *star_packed, const double *Aplus, const double *Aminus,
+                    const int32_t *neigh, const uint8_t *face_rot, void *Q, hipStream_t stream);
+
+/* Waits for the stream; reports asynchronous kernel failures as DG_EHIP. */
+int dg_sync(hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

@@ -131,9 +131,10 @@ def godunov_face_matrices(matL, matR):
     return AL - W, W
 
 
-def flux_matrices(X, materials, neigh):
+def flux_matrices(X, materials, neigh, neighbour_materials=None):
     """(Aplus, Aminus), each (E, 4, 9, 9), in the form used by the update:
-    Q += sum_s Rhat^s (R^s^T I) Aplus^s^T + neighbour analogue with Aminus."""
+    Q += sum_s Rhat^s (R^s^T I) Aplus^s^T + neighbour analogue with Aminus.
+    neighbour_materials (E, 4, 3), if given, replaces materials[neigh]."""
     E = X.shape[0]
     _, det, _ = geometry(X)
     n, s, t, area = face_frames(X)
@@ -141,7 +142,7 @@ def flux_matrices(X, materials, neigh):
     T = rotation_9x9(Qm)
     Tinv = rotation_9x9(np.swapaxes(Qm, -1, -2))
     matL = np.broadcast_to(materials[:, None, :], (E, 4, 3))
-    matR = materials[neigh]
+    matR = materials[neigh] if neighbour_materials is None else neighbour_materials
     Ap, Am = godunov_face_matrices(matL, matR)
     scale = -(2.0 * area / det[:, None])[..., None, None]
     Aplus = scale * (T @ Ap @ Tinv)

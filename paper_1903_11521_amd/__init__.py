@@ -1,0 +1,13 @@
+"""MI355X-native elastic ADER-DG element kernels (Python binding).
+
+Thin ctypes binding of the C ABI declared in include/dg.h.  Argument
+marshalling only: every stage of the scheme runs in the HIP library
+(libdg_mi355x.so, built in-tree by paper_1903_11521_amd/build.py).  PyTorch
+provides device memory and the current stream.  There is no CPU fallback: if
+the library is missing, every call raises.
+"""
+from ._lib import (DG_FP32, DG_FP64, DGError, Plan, element_data, library_path,
+                   reference_matrices, flop_model, byte_model)
+
+__all__ = ["Plan", "DGError", "DG_FP64", "DG_FP32", "reference_matrices", "element_data",
+           "library_path", "flop_model", "byte_model"]

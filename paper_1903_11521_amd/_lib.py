@@ -1,0 +1,305 @@
+"""ctypes binding of include/dg.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from math import comb
+
+import numpy as np
+
+DG_FP64 = 0
+DG_FP32 = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libdg_mi355x.so"
+_lock = threading.Lock()
+_lib = None
+
+
+class DGError(RuntimeError):
+    pass
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        path = library_path()
+        if not os.path.exists(path):
+            raise DGError("HIP library %s is not built (run paper_1903_11521_amd/build.py); "
+                          "there is no CPU fallback" % path)
+        lib = ctypes.CDLL(path)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.dg_last_error.restype = ctypes.c_char_p
+        lib.dg_reference_blob_size.restype = i64
+        lib.dg_reference_blob_size.argtypes = [i32]
+        lib.dg_reference_matrices.argtypes = [i32, dp]
+        lib.dg_element_data_host.argtypes = [i64, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp, dp]
+        lib.dg_plan_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
+        lib.dg_plan_destroy.argtypes = [vp]
+        lib.dg_plan_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.dg_pack_star.argtypes = [vp, i64, vp, vp, vp]
+        lib.dg_predictor.argtypes = [vp, i64, dbl, vp, vp, vp, vp]
+        lib.dg_time_integral.argtypes = [vp, i64, dbl, vp, vp, vp]
+        lib.dg_volume.argtypes = [vp, i64, vp, vp, vp, vp]
+        lib.dg_local_flux.argtypes = [vp, i64, vp, vp, vp, vp]
+        lib.dg_neighbour_flux.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
+        lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_step_predict.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp]
+        lib.dg_step_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_sync.argtypes = [vp]
+        _lib = lib
+        return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise DGError("dg error %d: %s" % (rc, _load().dg_last_error().decode(errors="replace")))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------------------
+# host helpers
+# ---------------------------------------------------------------------------
+def reference_matrices(degree: int) -> dict:
+    lib = _load()
+    n = lib.dg_reference_blob_size(degree)
+    if n <= 0:
+        raise DGError("unsupported degree %d" % degree)
+    buf = np.zeros(n)
+    _check(lib.dg_reference_matrices(degree, _dptr(buf)))
+    B, Bf = comb(degree + 3, 3), comb(degree + 2, 2)
+    out, o = {}, 0
+    for name, shape in (("Khat", (3, B, B)), ("Ktilde", (3, B, B)), ("R", (4, B, Bf)), ("Rhat", (4, B, Bf)),
+                        ("f", (3, Bf, Bf)), ("mass", (B,)), ("face_mass", (Bf,))):
+        sz = int(np.prod(shape))
+        out[name] = buf[o:o + sz].reshape(shape).copy()
+        o += sz
+    return out
+
+
+def element_data(X, materials, neigh):
+    """Star matrices (E,3,9,9) and flux solvers A+, A- (E,4,9,9) on the host."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    mats = np.ascontiguousarray(materials, dtype=np.float64)
+    nb = np.ascontiguousarray(neigh, dtype=np.int32)
+    E = X.shape[0]
+    if X.shape != (E, 4, 3) or mats.shape != (E, 3) or nb.shape != (E, 4):
+        raise ValueError("element_data: expected X (E,4,3), materials (E,3), neigh (E,4)")
+    star = np.empty((E, 3, 9, 9))
+    Ap = np.empty((E, 4, 9, 9))
+    Am = np.empty((E, 4, 9, 9))
+    _check(lib.dg_element_data_host(E, _dptr(X), _dptr(mats), nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    _dptr(star), _dptr(Ap), _dptr(Am)))
+    return star, Ap, Am
+
+
+def _nnz_models(degree):
+    M = reference_matrices(degree)
+    N = degree
+    bd = [comb(N - d + 3, 3) for d in range(N + 1)]
+    Bv = comb(N + 2, 3)
+    nk = sum(int(np.count_nonzero(M["Ktilde"][:, :, :bd[d]])) for d in range(N))
+    return M, bd, Bv, nk
+
+
+def flop_model(degree: int, orient_counts=None) -> dict:
+    """Non-zero flops per element of the kernels of one time step (the
+    paper's counting: one multiply and one add per structural non-zero
+    product, Sec. 4.3), for the algorithm this library runs.
+    orient_counts: fraction of faces with orientation h=0,1,2 (default uniform)."""
+    M, bd, Bv, nk = _nnz_models(degree)
+    N = degree
+    B = bd[0]
+    Bf = comb(N + 2, 2)
+    w = np.full(3, 1 / 3) if orient_counts is None else np.asarray(orient_counts, float)
+    star_nnz = 24
+    ck = sum(2 * 3 * star_nnz * bd[d] for d in range(N)) + 2 * 9 * nk
+    ti = sum(2 * 9 * bd[d] for d in range(N + 1))
+    traces = 2 * 9 * sum(int(np.count_nonzero(M["R"][s])) for s in range(4))
+    vol = 2 * 3 * star_nnz * Bv + 2 * 9 * int(np.count_nonzero(M["Khat"]))
+    lift = 2 * 9 * sum(int(np.count_nonzero(M["Rhat"][s])) for s in range(4))
+    mix = 4 * 2 * 81 * Bf
+    fh = 4 * 2 * 9 * float(np.dot(w, [np.count_nonzero(M["f"][h]) for h in range(3)]))
+    predict = ck + ti + traces
+    correct = vol + 2 * (lift + mix) + fh
+    return dict(ck=ck, ti=ti, traces=traces, volume=vol, local=lift + mix, neighbour=lift + mix + fh,
+                step_predict=predict, step_correct=correct, step=predict + correct, B=B, Bf=Bf)
+
+
+def byte_model(degree: int, itemsize: int = 8) -> dict:
+    """Algorithmic HBM bytes per element of the two step kernels: every array
+    read or written once (neighbour traces with ideal reuse); A+/A- FP64."""
+    N = degree
+    B, Bf = comb(N + 3, 3), comb(N + 2, 2)
+    q = 9 * B * itemsize
+    tr = 4 * 9 * Bf * itemsize
+    star = 81 * itemsize
+    flux = 2 * 4 * 81 * 8
+    tables = 4 * 4 + 4
+    predict = q + star + q + tr                      # Q, star -> I, traces
+    correct = q + tr + tr + star + flux + tables + q + q   # I, own+nbr traces, star, A+-, tables, Q rw
+    return dict(step_predict=predict, step_correct=correct, step=predict + correct)
+
+
+# ---------------------------------------------------------------------------
+# device plans (torch tensors for memory and streams)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A compiled (degree, precision) configuration of the element kernels."""
+
+    def __init__(self, degree: int, precision: int = DG_FP64):
+        lib = _load()
+        h = ctypes.c_void_p()
+        _check(lib.dg_plan_create(degree, precision, ctypes.byref(h)))
+        self._h = h
+        self.degree = degree
+        self.precision = precision
+        B, Bf = ctypes.c_int(), ctypes.c_int()
+        _check(lib.dg_plan_sizes(h, ctypes.byref(B), ctypes.byref(Bf)))
+        self.B, self.Bf = B.value, Bf.value
+        torch = _torch()
+        self.dtype = torch.float64 if precision == DG_FP64 else torch.float32
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.dg_plan_destroy(self._h)
+            self._h = None
+
+    # -- argument helpers ----------------------------------------------------
+    def _t(self, t, shape, dtype, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+        if t.dtype != dtype:
+            raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous device tensor" % name)
+        return ctypes.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def _stream(stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    # -- shapes --------------------------------------------------------------
+    def dof_shape(self, E):
+        return (E, 9, self.B)
+
+    def trace_shape(self, E):
+        return (E, 4, 9, self.Bf)
+
+    def deriv_shape(self, E):
+        return (E, self.degree + 1, 9, self.B)
+
+    # -- calls ---------------------------------------------------------------
+    def pack_star(self, star_dense, out=None, stream=None):
+        torch = _torch()
+        E = star_dense.shape[0]
+        if out is None:
+            out = torch.empty((E, 9, 3, 3), dtype=self.dtype, device=star_dense.device)
+        _check(_load().dg_pack_star(self._h, E, self._t(star_dense, (E, 3, 9, 9), torch.float64, "star_dense"),
+                                    self._t(out, (E, 9, 3, 3), self.dtype, "star_packed"), self._stream(stream)))
+        return out
+
+    def predictor(self, Q, star_packed, dt, T=None, stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        if T is None:
+            T = torch.empty(self.deriv_shape(E), dtype=self.dtype, device=Q.device)
+        _check(_load().dg_predictor(self._h, E, float(dt), self._t(Q, self.dof_shape(E), self.dtype, "Q"),
+                                    self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                    self._t(T, self.deriv_shape(E), self.dtype, "T"), self._stream(stream)))
+        return T
+
+    def time_integral(self, T, dt, I=None, stream=None):
+        torch = _torch()
+        E = T.shape[0]
+        if I is None:
+            I = torch.empty(self.dof_shape(E), dtype=self.dtype, device=T.device)
+        _check(_load().dg_time_integral(self._h, E, float(dt), self._t(T, self.deriv_shape(E), self.dtype, "T"),
+                                        self._t(I, self.dof_shape(E), self.dtype, "I"), self._stream(stream)))
+        return I
+
+    def volume(self, I, star_packed, Q, stream=None):
+        E = Q.shape[0]
+        _check(_load().dg_volume(self._h, E, self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                 self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                 self._t(Q, self.dof_shape(E), self.dtype, "Q"), self._stream(stream)))
+        return Q
+
+    def local_flux(self, I, Aplus, Q, stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_local_flux(self._h, E, self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                     self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                                     self._t(Q, self.dof_shape(E), self.dtype, "Q"), self._stream(stream)))
+        return Q
+
+    def neighbour_flux(self, I, neigh, face_rot, Aminus, Q, stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        EI = I.shape[0]
+        _check(_load().dg_neighbour_flux(self._h, E, EI, self._t(I, self.dof_shape(EI), self.dtype, "I"),
+                                         self._t(neigh, (E, 4), torch.int32, "neigh"),
+                                         self._t(face_rot, (E, 4), torch.uint8, "face_rot"),
+                                         self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                                         self._t(Q, self.dof_shape(E), self.dtype, "Q"), self._stream(stream)))
+        return Q
+
+    def step(self, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, dt, n_steps=1, stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_step(self._h, E, float(dt), int(n_steps),
+                               self._t(Q, self.dof_shape(E), self.dtype, "Q"),
+                               self._t(I, self.dof_shape(E), self.dtype, "I"),
+                               self._t(traces, self.trace_shape(E), self.dtype, "traces"),
+                               self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                               self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                               self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                               self._t(neigh, (E, 4), torch.int32, "neigh"),
+                               self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
+        return Q
+
+    def step_predict(self, Q, star_packed, dt, I, traces, stream=None):
+        E = Q.shape[0]
+        _check(_load().dg_step_predict(self._h, E, float(dt), self._t(Q, self.dof_shape(E), self.dtype, "Q"),
+                                       self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                       self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                       self._t(traces, self.trace_shape(E), self.dtype, "traces"),
+                                       self._stream(stream)))
+
+    def step_correct(self, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, Q, stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_step_correct(self._h, E, self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                       self._t(traces, self.trace_shape(E), self.dtype, "traces"),
+                                       self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                       self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                                       self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                                       self._t(neigh, (E, 4), torch.int32, "neigh"),
+                                       self._t(face_rot, (E, 4), torch.uint8, "face_rot"),
+                                       self._t(Q, self.dof_shape(E), self.dtype, "Q"), self._stream(stream)))
+
+    @staticmethod
+    def sync(stream=None):
+        _check(_load().dg_sync(Plan._stream(stream)))

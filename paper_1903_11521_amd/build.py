@@ -1,0 +1,96 @@
+"""Build the gfx950 element-kernel library in-tree.
+
+Steps: (1) host-only build of the reference-matrix generator, (2) code
+generation of the sparse contraction code from those matrices, (3) hipcc of
+one translation unit per polynomial degree plus the host C ABI, (4) link
+into paper_1903_11521_amd/libdg_mi355x.so.
+"""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+GEN = os.path.join(BUILD, "gen")
+LIB = os.path.join(PKG, "libdg_mi355x.so")
+DEGREES = (2, 3, 4, 5, 6)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + GEN]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build step failed: %s\n%s" % (" ".join(cmd), r.stdout[-6000:]))
+    return r.stdout
+
+
+def kernel_usage(text):
+    """Per-kernel VGPR/AGPR/scratch/occupancy from the compiler's resource remarks."""
+    usage, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            usage[cur] = {}
+            continue
+        m = re.search(r"(VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]): (\d+)", line)
+        if m and cur:
+            usage[cur][m.group(1).split(" ")[0]] = int(m.group(2))
+    return usage
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(GEN, exist_ok=True)
+    host = os.path.join(BUILD, "librefmat_host.so")
+    _run(["g++", "-O2", "-shared", "-fPIC", "-DDG_REFMAT_STANDALONE", os.path.join(CSRC, "refmat.cpp"),
+          "-o", host])
+    sys.path.insert(0, PKG)
+    try:
+        import codegen  # noqa: E402  (build-time helper beside this file)
+    finally:
+        sys.path.pop(0)
+    codegen.generate(host, os.path.join(GEN, "dg_generated.h"))
+    objs = []
+    cmds = []
+    for n in DEGREES:
+        o = os.path.join(BUILD, "dg_launch_%d.o" % n)
+        cmds.append([HIPCC] + HIP_FLAGS + ["-DDG_DEGREE=%d" % n, "-Rpass-analysis=kernel-resource-usage",
+                                           "-c", os.path.join(CSRC, "dg_launch.hip"), "-o", o])
+        objs.append(o)
+    for src in ("dg_api.cpp", "refmat.cpp", "elements.cpp"):
+        o = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with ThreadPoolExecutor(jobs) as ex:
+        outs = list(ex.map(_run, cmds))
+    usage = kernel_usage("\n".join(outs))
+    spills = {k: v for k, v in usage.items() if v.get("ScratchSize", 0) > 0}
+    if spills:
+        raise RuntimeError("kernels spill to scratch memory: %s" % sorted(spills))
+    with open(os.path.join(BUILD, "kernel_usage.txt"), "w") as fh:
+        for name, v in sorted(usage.items()):
+            fh.write("%s %s\n" % (name, " ".join("%s=%s" % kv for kv in sorted(v.items()))))
+    if verbose:
+        for o in outs:
+            if o.strip():
+                print(o)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

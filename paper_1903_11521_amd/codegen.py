@@ -1,0 +1,232 @@
+"""Build-time generator of the sparse element-kernel code.
+
+The reference matrices are element independent, so their sparsity pattern and
+values are compile-time constants (the paper stores such matrices inside the
+generated code, Sec. 4.9).  This script asks the library's own host generator
+(csrc/refmat.cpp, loaded through a small host-only shared object) for the
+matrices of every supported degree and writes `dg_generated.h`:
+
+  * `__constant__` arrays holding the non-zeros of K-tilde, K-hat, R, R-hat
+    and f in the order the kernels consume them (double and float copies),
+  * per-column functors that apply one column of a matrix to register arrays
+    with fully unrolled FMAs (one FMA per non-zero; the matrix entry is a
+    scalar load from the constant array at a compile-time offset).
+
+Column order conventions (matching the consumption order of the kernels):
+  KtCol<N,L>    acc[k] += Kt^d[k][L] * x_d           (predictor, d = 0..2)
+  KhCol<N,L>    acc[k] += Kh^d[k][L] * x_d           (volume)
+  RCol<N,S,L>   tr[m]  += R^S[L][m]  * v             (face trace of row L)
+  RhCol<N,S,M>  acc[k] += Rh^S[k][M] * g             (lift of face row M)
+  FApply<N,H>   out[m]  = sum_n f^H[m][n] in[n]      (orientation change)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+DEGREES = (2, 3, 4, 5, 6)
+
+
+def load_host(lib_path):
+    lib = ctypes.CDLL(lib_path)
+    lib.dg_reference_blob_size.restype = ctypes.c_int64
+    lib.dg_reference_blob_size.argtypes = [ctypes.c_int]
+    lib.dg_reference_matrices.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    return lib
+
+
+def matrices(lib, N):
+    n = lib.dg_reference_blob_size(N)
+    buf = np.zeros(n)
+    rc = lib.dg_reference_matrices(N, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError("reference matrix generation failed")
+    B = (N + 1) * (N + 2) * (N + 3) // 6
+    Bf = (N + 1) * (N + 2) // 2
+    o = 0
+
+    def take(shape):
+        nonlocal o
+        sz = int(np.prod(shape))
+        a = buf[o:o + sz].reshape(shape)
+        o += sz
+        return a
+
+    return dict(B=B, Bf=Bf, Kh=take((3, B, B)), Kt=take((3, B, B)), R=take((4, B, Bf)),
+                Rh=take((4, B, Bf)), f=take((3, Bf, Bf)))
+
+
+def _lit(v):
+    return repr(float(v))
+
+
+class Emitter:
+    def __init__(self):
+        self.lines = []
+
+    def __call__(self, s=""):
+        self.lines.append(s)
+
+
+def _degrees(N):
+    return [i + j + k for dd in range(N + 1) for k in range(dd + 1) for j in range(dd - k + 1)
+            for i in (dd - j - k,)]
+
+
+def check_structure(N, M):
+    """Properties the kernels rely on: Kt^d[k][l] != 0 only for deg(k) <
+    deg(l) (derivative staircase) and Kh non-zero only in the first
+    C(N+2,3) columns."""
+    deg = np.array(_degrees(N))
+    for d in range(3):
+        k, l = np.nonzero(M["Kt"][d])
+        if not np.all(deg[k] < deg[l]):
+            raise RuntimeError("Ktilde breaks the staircase structure")
+        k, l = np.nonzero(M["Kh"][d])
+        if len(l) and l.max() >= N * (N + 1) * (N + 2) // 6:
+            raise RuntimeError("Khat has non-zeros beyond the degree N-1 columns")
+
+
+def gen_degree(em, N, M):
+    check_structure(N, M)
+    B, Bf = M["B"], M["Bf"]
+    consts = {}
+
+    def add(name, vals):
+        consts[name] = vals
+
+    # K-tilde, column(L)-major, then d, then k
+    for key, nm in (("Kt", "KtCol"), ("Kh", "KhCol")):
+        A = M[key]
+        vals = []
+        bodies = []
+        for L in range(B):
+            stm = []
+            for d in range(3):
+                for k in range(B):
+                    v = A[d, k, L]
+                    if v != 0.0:
+                        stm.append(f"acc[{k}] = fma(c[{len(vals)}], x{d}, acc[{k}]);")
+                        vals.append(v)
+            bodies.append(stm)
+        cname = f"g_{key}{N}"
+        add(cname, vals)
+        for L in range(B):
+            em(f"template <> struct {nm}<{N}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c0, real x0, real x1, real x2, real* __restrict__ acc) {{")
+            if bodies[L]:
+                em("  const real* c = c0;")
+            for s in bodies[L]:
+                em("  " + s)
+            em("} };")
+    # R: trace, row(L)-major per face S, then m
+    for S in range(4):
+        vals = []
+        for L in range(B):
+            stm = []
+            for m in range(Bf):
+                v = M["R"][S, L, m]
+                if v != 0.0:
+                    stm.append(f"tr[{m}] = fma(c[{len(vals)}], v, tr[{m}]);")
+                    vals.append(v)
+            em(f"template <> struct RCol<{N}, {S}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, real v, real* __restrict__ tr) {{")
+            for s in stm:
+                em("  " + s)
+            em("} };")
+        add(f"g_R{N}_{S}", vals)
+    # R-hat: lift, column(M)-major per face, then k
+    for S in range(4):
+        vals = []
+        for Mi in range(Bf):
+            stm = []
+            for k in range(B):
+                v = M["Rh"][S, k, Mi]
+                if v != 0.0:
+                    stm.append(f"acc[{k}] = fma(c[{len(vals)}], g, acc[{k}]);")
+                    vals.append(v)
+            em(f"template <> struct RhCol<{N}, {S}, {Mi}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, real g, real* __restrict__ acc) {{")
+            for s in stm:
+                em("  " + s)
+            em("} };")
+        add(f"g_Rh{N}_{S}", vals)
+    # f^h: full apply
+    for H in range(3):
+        vals = []
+        em(f"template <> struct FApply<{N}, {H}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, const real* __restrict__ in, real* __restrict__ out) {{")
+        for m in range(Bf):
+            terms = [(n, M["f"][H, m, n]) for n in range(Bf) if M["f"][H, m, n] != 0.0]
+            if not terms:
+                em(f"  out[{m}] = real(0);")
+                continue
+            n0, v0 = terms[0]
+            em(f"  out[{m}] = c[{len(vals)}] * in[{n0}];")
+            vals.append(v0)
+            for n, v in terms[1:]:
+                em(f"  out[{m}] = fma(c[{len(vals)}], in[{n}], out[{m}]);")
+                vals.append(v)
+        em("} };")
+        add(f"g_F{N}_{H}", vals)
+    return consts
+
+
+def flop_counts(M, N):
+    """Non-zero multiply-add pairs per element-column of the generated code."""
+    B, Bf = M["B"], M["Bf"]
+    bd = [(N - d + 1) * (N - d + 2) * (N - d + 3) // 6 for d in range(N + 1)]
+    ck = sum(int(np.count_nonzero(M["Kt"][:, :, :bd[d]])) for d in range(N))
+    vol = int(np.count_nonzero(M["Kh"]))
+    r = [int(np.count_nonzero(M["R"][s])) for s in range(4)]
+    rh = [int(np.count_nonzero(M["Rh"][s])) for s in range(4)]
+    f = [int(np.count_nonzero(M["f"][h])) for h in range(3)]
+    return dict(ck=ck, vol=vol, R=r, Rh=rh, f=f, bd=bd)
+
+
+def generate(host_lib_path, out_path):
+    lib = load_host(host_lib_path)
+    em = Emitter()
+    em("// GENERATED by codegen.py from the library's reference-matrix generator. Do not edit.")
+    em("#pragma once")
+    em("template <int N, int L> struct KtCol;")
+    em("template <int N, int L> struct KhCol;")
+    em("template <int N, int S, int L> struct RCol;")
+    em("template <int N, int S, int M> struct RhCol;")
+    em("template <int N, int H> struct FApply;")
+    allc = {}
+    stats = {}
+    for N in DEGREES:
+        M = matrices(lib, N)
+        allc.update(gen_degree(em, N, M))
+        stats[N] = flop_counts(M, N)
+    body = em.lines
+    em2 = Emitter()
+    em2.lines = body[:7]
+    for name, vals in allc.items():
+        n = max(1, len(vals))
+        vd = ", ".join(_lit(v) for v in vals) or "0.0"
+        em2(f"__constant__ double {name}_d[{n}] = {{{vd}}};")
+        em2(f"__constant__ float {name}_f[{n}] = {{{', '.join(_lit(np.float32(v)) + 'f' for v in vals) or '0.0f'}}};")
+    em2("template <typename real, int N> __device__ const real* gKt();")
+    em2("template <typename real, int N> __device__ const real* gKh();")
+    em2("template <typename real, int N, int S> __device__ const real* gR();")
+    em2("template <typename real, int N, int S> __device__ const real* gRh();")
+    em2("template <typename real, int N, int H> __device__ const real* gF();")
+    for tname, suf in (("double", "d"), ("float", "f")):
+        for N in DEGREES:
+            em2(f"template <> __device__ __forceinline__ const {tname}* gKt<{tname}, {N}>() {{ return g_Kt{N}_{suf}; }}")
+            em2(f"template <> __device__ __forceinline__ const {tname}* gKh<{tname}, {N}>() {{ return g_Kh{N}_{suf}; }}")
+            for S in range(4):
+                em2(f"template <> __device__ __forceinline__ const {tname}* gR<{tname}, {N}, {S}>() {{ return g_R{N}_{S}_{suf}; }}")
+                em2(f"template <> __device__ __forceinline__ const {tname}* gRh<{tname}, {N}, {S}>() {{ return g_Rh{N}_{S}_{suf}; }}")
+            for H in range(3):
+                em2(f"template <> __device__ __forceinline__ const {tname}* gF<{tname}, {N}, {H}>() {{ return g_F{N}_{H}_{suf}; }}")
+    em2.lines += body[7:]
+    with open(out_path + ".tmp", "w") as fh:
+        fh.write("\n".join(em2.lines) + "\n")
+    os.replace(out_path + ".tmp", out_path)
+    return stats
+
+
+if __name__ == "__main__":
+    generate(sys.argv[1], sys.argv[2])

@@ -1,0 +1,555 @@
+// Element-local ADER-DG kernels for the elastic wave equation on tetrahedra
+// (paper Sec. 5.1.1, Eqs. seissol:derivative, seissol:timeint,
+// seissol:correction_local, seissol:correction_neigh), written for CDNA4.
+//
+// Work decomposition: one 64-lane wavefront per workgroup handles 7
+// elements; lane = (element e, quantity p), lane 63 shadows element 7 and
+// never stores.  A lane owns one column (basis coefficients of quantity p)
+// of its element.  Contractions with the element-independent reference
+// matrices act column-wise and run as fully unrolled FP64/FP32 FMAs whose
+// matrix operand is a scalar-cache constant (generated from the sparsity of
+// each matrix, so structural zeros cost nothing).  Contractions over the
+// quantity index (star matrices, flux solvers) mix columns; those go through
+// a 16-row LDS chunk buffer.  All global traffic of element-major arrays is
+// staged through the same buffer so that it is fully coalesced.
+//
+// Arrays are element major: Q, I [E][9][B]; T [E][N+1][9][B] (Taylor-scaled
+// derivatives dt^d/d! D^d); traces [E][4][9][Bf]; packed star [E][9][3][3];
+// flux solvers A+/A- [E][4][9][9] FP64.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "dg_generated.h"
+
+namespace dgk {
+
+constexpr int EPW = 7;     // elements per wavefront
+constexpr int NQ = 9;      // elastic quantities
+constexpr int CH = 16;     // rows per LDS chunk
+constexpr int LB = CH + 1; // padded row stride of a column in LDS
+constexpr int NCOL = 8 * NQ;
+
+__host__ __device__ constexpr int nb3(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
+__host__ __device__ constexpr int nb2(int n) { return (n + 1) * (n + 2) / 2; }
+
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, E>(f);
+    }
+}
+
+// q-columns read by row p of the packed star matrix (elastic pattern:
+// stress rows couple to velocities, velocity rows to stresses)
+__device__ __forceinline__ void star_cols(int p, int &q0, int &q1, int &q2)
+{
+    switch (p) {
+    case 0: case 1: case 2: q0 = 6; q1 = 7; q2 = 8; break;
+    case 3: q0 = 6; q1 = 7; q2 = 6; break;
+    case 4: q0 = 7; q1 = 8; q2 = 7; break;
+    case 5: q0 = 6; q1 = 8; q2 = 6; break;
+    case 6: q0 = 0; q1 = 3; q2 = 5; break;
+    case 7: q0 = 1; q1 = 3; q2 = 4; break;
+    default: q0 = 2; q1 = 4; q2 = 5; break;
+    }
+}
+
+template <typename real>
+struct Lane {
+    int lane, e, p;
+    int64_t base, elem;
+    bool active;
+    real *buf;      // LDS chunk buffer [8][9][LB]
+    real *own;      // this lane's column in buf
+};
+
+template <typename real>
+__device__ __forceinline__ Lane<real> make_lane(real *buf, int64_t E)
+{
+    Lane<real> L;
+    L.lane = threadIdx.x;
+    L.e = L.lane / NQ;
+    L.p = L.lane - L.e * NQ;
+    // XCD-aware block order: consecutive element ranges stay on one XCD
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t full = (nb >> 3) << 3;
+    const int64_t lb = b < full ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+    L.base = lb * EPW;
+    const int64_t el = L.base + L.e;
+    L.active = (L.e < EPW) && (el < E);
+    L.elem = el < E ? el : E - 1;
+    L.buf = buf;
+    L.own = buf + (L.e * NQ + L.p) * LB;
+    return L;
+}
+
+__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+// element of column slot c (0..71) of this wave, clamped into range
+__device__ __forceinline__ int64_t slot_elem(int64_t base, int c, int64_t E)
+{
+    const int64_t el = base + c / NQ;
+    return el < E ? el : E - 1;
+}
+
+// Cooperative, coalesced load of rows [l0, l0+cnt) of every column slot into
+// LDS.  colptr(c) returns the global address of row 0 of column slot c.
+template <int CNT, typename real, typename SrcT, typename ColPtr>
+__device__ __forceinline__ void chunk_load(const Lane<real> &L, ColPtr colptr, int l0)
+{
+    for (int idx = L.lane; idx < NCOL * CNT; idx += 64) {
+        const int c = idx / CNT, r = idx - c * CNT;
+        const SrcT *src = colptr(c);
+        L.buf[c * LB + r] = src ? (real)src[l0 + r] : real(0);
+    }
+}
+
+// Cooperative, coalesced store of rows [l0, l0+cnt) of the real (non-shadow,
+// in-range) column slots from LDS.
+template <int CNT, typename real, typename ColPtr>
+__device__ __forceinline__ void chunk_store(const Lane<real> &L, ColPtr colptr, int l0, int64_t E)
+{
+    for (int idx = L.lane; idx < EPW * NQ * CNT; idx += 64) {
+        const int c = idx / CNT, r = idx - c * CNT;
+        if (L.base + c / NQ < E) colptr(c)[l0 + r] = L.buf[c * LB + r];
+    }
+}
+
+// load this lane's own column (rows [0,R)) of an element-major array into regs
+template <int R, typename real, typename SrcT, typename ColPtr>
+__device__ __forceinline__ void load_columns(const Lane<real> &L, ColPtr colptr, real *dst)
+{
+    static_for<0, (R + CH - 1) / CH>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH;
+        constexpr int cnt = (R - l0) < CH ? (R - l0) : CH;
+        chunk_load<cnt, real, SrcT>(L, colptr, l0);
+        lds_sync();
+        static_for<0, cnt>([&](auto ri) { dst[l0 + ri] = L.own[ri]; });
+        lds_sync();
+    });
+}
+
+// store this lane's own column rows [0,R) from regs (rows >= RV written as 0)
+template <int R, int RV, typename real, typename ColPtr>
+__device__ __forceinline__ void store_columns(const Lane<real> &L, ColPtr colptr, const real *src, int64_t E)
+{
+    static_for<0, (R + CH - 1) / CH>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH;
+        constexpr int cnt = (R - l0) < CH ? (R - l0) : CH;
+        static_for<0, cnt>([&](auto ri) {
+            constexpr int l = l0 + decltype(ri)::value;
+            if constexpr (l < RV) L.own[ri] = src[l];
+            else L.own[ri] = real(0);
+        });
+        lds_sync();
+        chunk_store<cnt>(L, colptr, l0, E);
+        lds_sync();
+    });
+}
+
+// Q(own column) += acc, rows [0,B)
+template <int B, typename real>
+__device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const real *acc, int64_t E)
+{
+    auto col = [&](int c) { return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
+    static_for<0, (B + CH - 1) / CH>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH;
+        constexpr int cnt = (B - l0) < CH ? (B - l0) : CH;
+        chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return col(c); }, l0);
+        lds_sync();
+        static_for<0, cnt>([&](auto ri) { L.own[ri] += acc[l0 + ri]; });
+        lds_sync();
+        chunk_store<cnt>(L, col, l0, E);
+        lds_sync();
+    });
+}
+
+template <typename real>
+struct Star {
+    real s[3][3];   // [d][slot]
+    int q0, q1, q2;
+};
+
+template <typename real>
+__device__ __forceinline__ Star<real> load_star(const Lane<real> &L, const real *star_packed)
+{
+    Star<real> S;
+    star_cols(L.p, S.q0, S.q1, S.q2);
+    const real *sp = star_packed + (L.elem * NQ + L.p) * 9;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) S.s[d][i] = sp[d * 3 + i];
+    return S;
+}
+
+// acc[k] += sum_d K^d[k][l] (sum_q star^d[p][q] X[l][q]) for rows l in
+// [0, NROWS) whose values sit in LDS chunk-wise; `fill(l0, cnt)` brings rows
+// [l0, l0+cnt) of all column slots into LDS.
+template <int N, bool KTILDE, int NROWS, typename real, typename Fill>
+__device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<real> &S, real *acc, Fill fill)
+{
+    const real *c = KTILDE ? gKt<real, N>() : gKh<real, N>();
+    static_for<0, (NROWS + CH - 1) / CH>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH;
+        constexpr int cnt = (NROWS - l0) < CH ? (NROWS - l0) : CH;
+        fill(std::integral_constant<int, l0>{}, std::integral_constant<int, cnt>{});
+        lds_sync();
+        const real *b0 = L.buf + (L.e * NQ + S.q0) * LB;
+        const real *b1 = L.buf + (L.e * NQ + S.q1) * LB;
+        const real *b2 = L.buf + (L.e * NQ + S.q2) * LB;
+        static_for<0, cnt>([&](auto ri) {
+            constexpr int l = l0 + decltype(ri)::value;
+            const real v0 = b0[ri], v1 = b1[ri], v2 = b2[ri];
+            const real x0 = fma(S.s[0][0], v0, fma(S.s[0][1], v1, S.s[0][2] * v2));
+            const real x1 = fma(S.s[1][0], v0, fma(S.s[1][1], v1, S.s[1][2] * v2));
+            const real x2 = fma(S.s[2][0], v0, fma(S.s[2][1], v1, S.s[2][2] * v2));
+            if constexpr (KTILDE) KtCol<N, l>::apply(c, x0, x1, x2, acc);
+            else KhCol<N, l>::apply(c, x0, x1, x2, acc);
+        });
+        lds_sync();
+    });
+}
+
+// acc[k] += sum_m Rh^S[k][m] sum_q A[p][q] X[m][q] for face rows m in [0,Bf)
+// with X chunk-wise in LDS (fill brings rows in).
+template <int N, int S, typename real, typename Fill>
+__device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, real *acc, Fill fill)
+{
+    constexpr int Bf = nb2(N);
+    real a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = (real)A[L.p * NQ + q];
+    const real *c = gRh<real, N, S>();
+    const real *xe = L.buf + L.e * NQ * LB;
+    static_for<0, (Bf + CH - 1) / CH>([&](auto ci) {
+        constexpr int m0 = decltype(ci)::value * CH;
+        constexpr int cnt = (Bf - m0) < CH ? (Bf - m0) : CH;
+        fill(std::integral_constant<int, m0>{}, std::integral_constant<int, cnt>{});
+        lds_sync();
+        static_for<0, cnt>([&](auto ri) {
+            constexpr int m = m0 + decltype(ri)::value;
+            real g = a[0] * xe[ri];
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) g = fma(a[q], xe[q * LB + ri], g);
+            RhCol<N, S, m>::apply(c, g, acc);
+        });
+        lds_sync();
+    });
+}
+
+template <int N, int S, typename real>
+__device__ __forceinline__ void face_trace(const real *I, real *tr)
+{
+    constexpr int B = nb3(N), Bf = nb2(N);
+    const real *c = gR<real, N, S>();
+#pragma unroll
+    for (int m = 0; m < Bf; ++m) tr[m] = real(0);
+    static_for<0, B>([&](auto li) { RCol<N, S, decltype(li)::value>::apply(c, I[decltype(li)::value], tr); });
+}
+
+template <int N, typename real>
+__device__ __forceinline__ void face_trace_rt(int j, const real *I, real *tr)
+{
+    switch (j) {
+    case 0: face_trace<N, 0>(I, tr); break;
+    case 1: face_trace<N, 1>(I, tr); break;
+    case 2: face_trace<N, 2>(I, tr); break;
+    default: face_trace<N, 3>(I, tr); break;
+    }
+}
+
+template <int N, typename real>
+__device__ __forceinline__ void orient_rt(int h, const real *in, real *out)
+{
+    if (h == 0) FApply<N, 0>::apply(gF<real, N, 0>(), in, out);
+    else if (h == 1) FApply<N, 1>::apply(gF<real, N, 1>(), in, out);
+    else FApply<N, 2>::apply(gF<real, N, 2>(), in, out);
+}
+
+// ---------------------------------------------------------------------------
+// Predictor (Eq. seissol:derivative) with the time integral (Eq.
+// seissol:timeint) accumulated on the fly.  T^0 = Q,
+// T^{d+1} = dt/(d+1) sum_xi Kt^xi T^d star^xi^T,  I = sum_d dt/(d+1) T^d.
+// ---------------------------------------------------------------------------
+template <int N, int D, bool WRITE_T, bool ACC_I, typename real, typename TColPtr>
+__device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real> &S, real dt, real *src,
+                                           real *I, TColPtr tcol, int64_t E)
+{
+    constexpr int B = nb3(N);
+    if constexpr (D < N) {
+        constexpr int bin = nb3(N - D), bout = nb3(N - D - 1);
+        real acc[bout];
+#pragma unroll
+        for (int k = 0; k < bout; ++k) acc[k] = real(0);
+        star_contract<N, true, bin>(L, S, acc, [&](auto l0c, auto cntc) {
+            constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
+            static_for<0, cnt>([&](auto ri) { L.own[ri] = src[l0 + ri]; });
+        });
+        if constexpr (ACC_I && D == 0) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) I[k] *= dt;     // src aliases I: T^0 = Q
+        }
+        const real sc = dt / real(D + 1), si = dt / real(D + 2);
+#pragma unroll
+        for (int k = 0; k < bout; ++k) {
+            acc[k] *= sc;
+            if constexpr (ACC_I) I[k] = fma(si, acc[k], I[k]);
+        }
+        if constexpr (WRITE_T) store_columns<B, bout>(L, [&](int c) { return tcol(c, D + 1); }, acc, E);
+        ck_recurse<N, D + 1, WRITE_T, ACC_I>(L, S, dt, acc, I, tcol, E);
+    }
+}
+
+// Per-stage predictor, one launch per derivative order D: reads T^D (or Q for
+// D = 0, which is also copied to T^0) and writes
+// T^{D+1} = dt/(D+1) sum_xi Kt^xi T^D star^xi^T (rows past the staircase 0).
+template <int N, int D, typename real>
+__global__ void __launch_bounds__(64) k_derivative(int64_t E, real dt, const real *__restrict__ Q,
+                                                   const real *__restrict__ star, real *__restrict__ T)
+{
+    constexpr int B = nb3(N), bin = nb3(N - D), bout = nb3(N - D - 1);
+    __shared__ real buf[NCOL * LB];
+    const Lane<real> L = make_lane(buf, E);
+    const Star<real> S = load_star(L, star);
+    auto tcol = [&](int c, int d) { return T + ((slot_elem(L.base, c, E) * (N + 1) + d) * NQ + c % NQ) * B; };
+    real acc[bout];
+#pragma unroll
+    for (int k = 0; k < bout; ++k) acc[k] = real(0);
+    star_contract<N, true, bin>(L, S, acc, [&](auto l0c, auto cntc) {
+        constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
+        if constexpr (D == 0) {
+            chunk_load<cnt, real, real>(L, [&](int c) -> const real * {
+                return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, l0);
+            lds_sync();
+            chunk_store<cnt>(L, [&](int c) { return tcol(c, 0); }, l0, E);
+        } else {
+            chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return tcol(c, D); }, l0);
+        }
+    });
+    const real sc = dt / real(D + 1);
+#pragma unroll
+    for (int k = 0; k < bout; ++k) acc[k] *= sc;
+    store_columns<B, bout>(L, [&](int c) { return tcol(c, D + 1); }, acc, E);
+}
+
+// Time integral over stored Taylor-scaled derivatives (FP64 accumulation).
+template <int N, typename real>
+__global__ void __launch_bounds__(256) k_time_integral(int64_t E, double dt, const real *__restrict__ T,
+                                                       real *__restrict__ I)
+{
+    constexpr int B = nb3(N);
+    const int64_t n = E * NQ * B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / (NQ * B), r = i - e * (NQ * B);
+        const real *t = T + e * (N + 1) * NQ * B + r;
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d <= N; ++d) s = fma(dt / double(d + 1), (double)t[d * NQ * B], s);
+        I[i] = (real)s;
+    }
+}
+
+// Volume term: Q += sum_xi Kh^xi I star^xi^T
+template <int N, typename real>
+__device__ __forceinline__ void volume_acc(const Lane<real> &L, const Star<real> &S, const real *I, real *acc, int64_t E)
+{
+    constexpr int B = nb3(N), Bv = nb3(N - 1);
+    star_contract<N, false, Bv>(L, S, acc, [&](auto l0c, auto cntc) {
+        constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
+        chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, l0);
+    });
+}
+
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_volume(int64_t E, const real *__restrict__ I, const real *__restrict__ star,
+                                               real *__restrict__ Q)
+{
+    constexpr int B = nb3(N);
+    __shared__ real buf[NCOL * LB];
+    const Lane<real> L = make_lane(buf, E);
+    const Star<real> S = load_star(L, star);
+    real acc[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) acc[k] = real(0);
+    volume_acc<N>(L, S, I, acc, E);
+    add_to_q<B>(L, Q, acc, E);
+}
+
+// Local flux: Q += sum_S Rh^S (R^S^T I) A+^S^T   (per-stage form: the trace
+// of each face is accumulated from I rows streamed through LDS)
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__restrict__ I, const double *__restrict__ Ap,
+                                                   real *__restrict__ Q)
+{
+    constexpr int B = nb3(N), Bf = nb2(N);
+    __shared__ real buf[NCOL * LB];
+    const Lane<real> L = make_lane(buf, E);
+    real acc[B], tr[Bf];
+#pragma unroll
+    for (int k = 0; k < B; ++k) acc[k] = real(0);
+    auto icol = [&](int c) -> const real * { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
+    static_for<0, 4>([&](auto si) {
+        constexpr int S = decltype(si)::value;
+        const real *cr = gR<real, N, S>();
+#pragma unroll
+        for (int m = 0; m < Bf; ++m) tr[m] = real(0);
+        static_for<0, (B + CH - 1) / CH>([&](auto ci) {
+            constexpr int l0 = decltype(ci)::value * CH;
+            constexpr int cnt = (B - l0) < CH ? (B - l0) : CH;
+            chunk_load<cnt, real, real>(L, icol, l0);
+            lds_sync();
+            static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(cr, L.own[ri], tr); });
+            lds_sync();
+        });
+        flux_lift<N, S>(L, Ap + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
+            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
+            static_for<0, cnt>([&](auto ri) { L.own[ri] = tr[m0 + ri]; });
+        });
+    });
+    add_to_q<B>(L, Q, acc, E);
+}
+
+// Neighbour flux: Q += sum_S Rh^S f^h (R^j^T I^nu) A-^S^T  (per-stage form)
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, const real *__restrict__ I,
+                                                       const int32_t *__restrict__ neigh,
+                                                       const uint8_t *__restrict__ face_rot,
+                                                       const double *__restrict__ Am, real *__restrict__ Q)
+{
+    constexpr int B = nb3(N), Bf = nb2(N);
+    __shared__ real buf[NCOL * LB];
+    __shared__ int nbt[8][4];
+    const Lane<real> L = make_lane(buf, E);
+    if (L.p == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int nu = neigh[L.elem * 4 + s];
+            nbt[L.e][s] = (nu >= 0 && nu < nI) ? nu : -1;   // out of range: no neighbour
+        }
+    }
+    lds_sync();
+    real In[B], acc[B], tr[Bf], t2[Bf];
+#pragma unroll
+    for (int k = 0; k < B; ++k) acc[k] = real(0);
+    static_for<0, 4>([&](auto si) {
+        constexpr int S = decltype(si)::value;
+        load_columns<B, real, real>(L, [&](int c) -> const real * {
+            const int nu = nbt[c / NQ][S];
+            return nu >= 0 ? I + ((int64_t)nu * NQ + c % NQ) * B : nullptr;
+        }, In);
+        const int nu = nbt[L.e][S];
+        const uint8_t fr = face_rot[L.elem * 4 + S];
+        face_trace_rt<N>(fr & 3, In, tr);   // In is zero when there is no neighbour
+        orient_rt<N>(fr >> 2, tr, t2);
+        if (nu < 0) {
+#pragma unroll
+            for (int m = 0; m < Bf; ++m) t2[m] = real(0);
+        }
+        flux_lift<N, S>(L, Am + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
+            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
+            static_for<0, cnt>([&](auto ri) { L.own[ri] = t2[m0 + ri]; });
+        });
+    });
+    add_to_q<B>(L, Q, acc, E);
+}
+
+// ---------------------------------------------------------------------------
+// Time step, part 1: predictor + time integral + face traces of I.
+// ---------------------------------------------------------------------------
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_step_predict(int64_t E, real dt, const real *__restrict__ Q,
+                                                     const real *__restrict__ star, real *__restrict__ I,
+                                                     real *__restrict__ traces)
+{
+    constexpr int B = nb3(N), Bf = nb2(N);
+    __shared__ real buf[NCOL * LB];
+    const Lane<real> L = make_lane(buf, E);
+    const Star<real> S = load_star(L, star);
+    real Ic[B];
+    load_columns<B, real, real>(L, [&](int c) -> const real * { return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, Ic);
+    auto nocol = [](int, int) { return (real *)nullptr; };
+    ck_recurse<N, 0, false, true>(L, S, dt, Ic, Ic, nocol, E);
+    store_columns<B, B>(L, [&](int c) { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, Ic, E);
+    real tr[Bf];
+    static_for<0, 4>([&](auto si) {
+        constexpr int Sf = decltype(si)::value;
+        face_trace<N, Sf>(Ic, tr);
+        store_columns<Bf, Bf>(L, [&](int c) { return traces + ((slot_elem(L.base, c, E) * 4 + Sf) * NQ + c % NQ) * Bf; }, tr, E);
+    });
+}
+
+// Time step, part 2: volume + local flux + neighbour flux -> Q.
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_step_correct(int64_t E, const real *__restrict__ I,
+                                                     const real *__restrict__ traces, const real *__restrict__ star,
+                                                     const double *__restrict__ Ap, const double *__restrict__ Am,
+                                                     const int32_t *__restrict__ neigh,
+                                                     const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
+{
+    constexpr int B = nb3(N), Bf = nb2(N);
+    __shared__ real buf[NCOL * LB];
+    __shared__ int nbt[8][4];
+    __shared__ int jt[8][4];
+    const Lane<real> L = make_lane(buf, E);
+    if (L.p == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int nu = neigh[L.elem * 4 + s];
+            nbt[L.e][s] = (nu >= 0 && nu < E) ? nu : -1;    // out of range: no neighbour
+            jt[L.e][s] = face_rot[L.elem * 4 + s] & 3;
+        }
+    }
+    lds_sync();
+    const Star<real> S = load_star(L, star);
+    real acc[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) acc[k] = real(0);
+    volume_acc<N>(L, S, I, acc, E);
+    static_for<0, 4>([&](auto si) {
+        constexpr int Sf = decltype(si)::value;
+        flux_lift<N, Sf>(L, Ap + (L.elem * 4 + Sf) * 81, acc, [&](auto m0c, auto cntc) {
+            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
+            chunk_load<cnt, real, real>(L, [&](int c) -> const real * {
+                return traces + ((slot_elem(L.base, c, E) * 4 + Sf) * NQ + c % NQ) * Bf; }, m0);
+        });
+    });
+    real tn[Bf], t2[Bf];
+    static_for<0, 4>([&](auto si) {
+        constexpr int Sf = decltype(si)::value;
+        load_columns<Bf, real, real>(L, [&](int c) -> const real * {
+            const int nu = nbt[c / NQ][Sf];
+            return nu >= 0 ? traces + (((int64_t)nu * 4 + jt[c / NQ][Sf]) * NQ + c % NQ) * Bf : nullptr;
+        }, tn);
+        const uint8_t fr = face_rot[L.elem * 4 + Sf];
+        orient_rt<N>(fr >> 2, tn, t2);
+        flux_lift<N, Sf>(L, Am + (L.elem * 4 + Sf) * 81, acc, [&](auto m0c, auto cntc) {
+            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
+            static_for<0, cnt>([&](auto ri) { L.own[ri] = t2[m0 + ri]; });
+        });
+    });
+    add_to_q<B>(L, Q, acc, E);
+}
+
+// dense star [E][3][9][9] (FP64) -> packed [E][9][3][3] (real)
+template <typename real>
+__global__ void k_pack_star(int64_t E, const double *__restrict__ dense, real *__restrict__ packed)
+{
+    const int64_t n = E * 81;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / 81;
+        const int r = i - e * 81, p = r / 9, d = (r % 9) / 3, s = r % 3;
+        int q0, q1, q2;
+        star_cols(p, q0, q1, q2);
+        const int q = s == 0 ? q0 : (s == 1 ? q1 : q2);
+        const bool pad = (s == 2) && (p >= 3 && p <= 5);
+        packed[i] = pad ? real(0) : (real)dense[((e * 3 + d) * 9 + p) * 9 + q];
+    }
+}
+
+}  // namespace dgk

@@ -1,0 +1,119 @@
+// Launchers of the element kernels for one polynomial degree (DG_DEGREE),
+// both precisions.  Compiled once per supported degree.
+#include "dg_kernels.hip"
+#include "dg_internal.h"
+
+#ifndef DG_DEGREE
+#error "DG_DEGREE must be defined"
+#endif
+
+namespace {
+
+constexpr int N = DG_DEGREE;
+
+inline unsigned wave_blocks(int64_t E) { return (unsigned)((E + dgk::EPW - 1) / dgk::EPW); }
+
+inline unsigned flat_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <typename real>
+struct Launch {
+    static hipError_t pack_star(int64_t E, const double *dense, void *packed, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL(dgk::k_pack_star<real>, dim3(flat_blocks(E * 81)), dim3(256), 0, s, E, dense,
+                           (real *)packed);
+        return hipGetLastError();
+    }
+    template <int D>
+    static hipError_t derivatives(int64_t E, double dt, const void *Q, const void *star, void *T, hipStream_t s)
+    {
+        if constexpr (D < N) {
+            hipLaunchKernelGGL((dgk::k_derivative<N, D, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (real)dt,
+                               (const real *)Q, (const real *)star, (real *)T);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return derivatives<D + 1>(E, dt, Q, star, T, s);
+        }
+        return hipSuccess;
+    }
+    static hipError_t predictor(int64_t E, double dt, const void *Q, const void *star, void *T, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        return derivatives<0>(E, dt, Q, star, T, s);
+    }
+    static hipError_t time_integral(int64_t E, double dt, const void *T, void *I, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_time_integral<N, real>), dim3(flat_blocks(E * 9 * dgk::nb3(N))), dim3(256), 0,
+                           s, E, dt, (const real *)T, (real *)I);
+        return hipGetLastError();
+    }
+    static hipError_t volume(int64_t E, const void *I, const void *star, void *Q, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_volume<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (const real *)I,
+                           (const real *)star, (real *)Q);
+        return hipGetLastError();
+    }
+    static hipError_t local_flux(int64_t E, const void *I, const double *Ap, void *Q, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_local_flux<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E,
+                           (const real *)I, Ap, (real *)Q);
+        return hipGetLastError();
+    }
+    static hipError_t neighbour_flux(int64_t E, int64_t nI, const void *I, const int32_t *neigh,
+                                     const uint8_t *fr, const double *Am, void *Q, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_neighbour_flux<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, nI,
+                           (const real *)I, neigh, fr, Am, (real *)Q);
+        return hipGetLastError();
+    }
+    static hipError_t step_predict(int64_t E, double dt, const void *Q, const void *star, void *I, void *traces,
+                                   hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_step_predict<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (real)dt,
+                           (const real *)Q, (const real *)star, (real *)I, (real *)traces);
+        return hipGetLastError();
+    }
+    static hipError_t step_correct(int64_t E, const void *I, const void *traces, const void *star,
+                                   const double *Ap, const double *Am, const int32_t *neigh, const uint8_t *fr,
+                                   void *Q, hipStream_t s)
+    {
+        if (E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_step_correct<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E,
+                           (const real *)I, (const real *)traces, (const real *)star, Ap, Am, neigh, fr,
+                           (real *)Q);
+        return hipGetLastError();
+    }
+    static void fill(DgTable *t)
+    {
+        t->pack_star = pack_star;
+        t->predictor = predictor;
+        t->time_integral = time_integral;
+        t->volume = volume;
+        t->local_flux = local_flux;
+        t->neighbour_flux = neighbour_flux;
+        t->step_predict = step_predict;
+        t->step_correct = step_correct;
+    }
+};
+
+}  // namespace
+
+#define DG_CAT2(a, b) a##b
+#define DG_CAT(a, b) DG_CAT2(a, b)
+
+void DG_CAT(dg_table_, DG_DEGREE)(DgTable *fp64, DgTable *fp32)
+{
+    Launch<double>::fill(fp64);
+    Launch<float>::fill(fp32);
+}

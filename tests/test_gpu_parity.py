@@ -1,0 +1,199 @@
+"""GPU parity: every stage and the full step through the C ABI against the
+FP64 oracle on the same seeded inputs.  FP64 bar 1e-12, FP32 bar 1e-5
+(relative Frobenius error per quantity, increments for update stages)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import dgtest
+from oracle import refmat, stages
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy() if t.is_floating_point() else t.cpu().numpy()
+
+
+def _plan(N, prec):
+    import paper_1903_11521_amd as dg
+    return dg.Plan(N, prec)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("N,E", [(2, 30), (3, 52), (4, 17), (5, 52), (6, 23)])
+def test_stages(N, E, prec):
+    _say(f"test_stages N={N} E={E} prec={prec}")
+    d = dgtest.random_stage_inputs(N, E, seed=100 + N)
+    rm = refmat.refmats(N)
+    plan = _plan(N, prec)
+    dt = 0.13
+    tol = TOL[prec]
+    fdt = plan.dtype
+    star_p = plan.pack_star(_dev(d["star"]))
+    # predictor (Taylor-scaled derivatives)
+    T = plan.predictor(_dev(d["Q"], fdt), star_p, dt)
+    D = stages.predictor(rm, d["star"], d["Q"])
+    scale = np.array([dt ** k / math.factorial(k) for k in range(N + 1)])
+    Tref = D * scale[None, :, None, None]
+    Tg = _host(T)
+    for k in range(N + 1):
+        assert dgtest.rel_err(Tg[:, k], Tref[:, k]) <= tol * (4 if k > 2 else 1), f"derivative {k}"
+    # time integral from the oracle's derivatives
+    I = plan.time_integral(_dev(Tref, fdt), dt)
+    assert dgtest.rel_err(_host(I), stages.time_integral(N, D, dt)) <= tol
+    # update stages as increments on Q = 0
+    Iin = _dev(d["I"], fdt)
+    zero = lambda: torch.zeros(plan.dof_shape(E), dtype=fdt, device="cuda:0")
+    q = plan.volume(Iin, star_p, zero())
+    assert dgtest.rel_err(_host(q), stages.volume(rm, d["star"], d["I"])) <= tol
+    q = plan.local_flux(Iin, _dev(d["Ap"]), zero())
+    assert dgtest.rel_err(_host(q), stages.local_flux(rm, d["Ap"], d["I"])) <= tol
+    q = plan.neighbour_flux(Iin, _dev(d["neigh"]), _dev(d["face_rot"]), _dev(d["Am"]), zero())
+    ref = stages.neighbour_flux(rm, d["Am"], d["I"], d["neigh"], d["nface"], d["orient"])
+    assert dgtest.rel_err(_host(q), ref) <= tol
+    # add-to-Q path with a non-zero Q
+    Q0 = _dev(d["Q"], fdt)
+    plan.volume(Iin, star_p, Q0)
+    inc = _host(Q0) - d["Q"].astype(np.float32 if prec else np.float64).astype(np.float64)
+    assert dgtest.rel_err(inc, stages.volume(rm, d["star"], d["I"])) <= tol * 10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_config0(prec):
+    """One full time step on the 8x8x8x6 = 3072-element jittered periodic mesh,
+    degree 3, random materials; element data built by the library itself."""
+    import paper_1903_11521_amd as dg
+    N = 3
+    _say(f"test_step_config0 prec={prec}")
+    mesh, mats, Q, dt = dgtest.mesh_inputs(8, N, 0)
+    E = mesh.E
+    rm = refmat.refmats(N)
+    ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+    ref = stages.step(rm, dt, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+    plan = dg.Plan(N, prec)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    Qg = _dev(Q, plan.dtype)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0")
+    plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
+              _dev(mesh.face_rot), dt, 1)
+    Q1 = _host(Qg)
+    Qin = Q.astype(np.float32).astype(np.float64) if prec else Q
+    assert dgtest.rel_err(Q1 - Qin, ref - Q) <= TOL[prec] * (10 if prec else 1)
+    assert dgtest.rel_err(Q1, ref) <= TOL[prec]
+
+
+def test_step_multi_relabelled_degree5():
+    """Three steps on a mesh with all 12 neighbour face/orientation cases."""
+    import paper_1903_11521_amd as dg
+    N = 5
+    _say("test_step_multi_relabelled_degree5")
+    mesh, mats, Q, dt = dgtest.mesh_inputs(4, N, 2, relabel=True)
+    rm = refmat.refmats(N)
+    ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+    ref = Q.copy()
+    for _ in range(3):
+        ref = stages.step(rm, dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+    plan = dg.Plan(N, 0)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    Qg = _dev(Q)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0")
+    plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
+              _dev(mesh.face_rot), dt, 3)
+    assert dgtest.rel_err(_host(Qg) - Q, ref - Q) <= 1e-12
+
+
+@pytest.mark.parametrize("E", [0, 1, 7, 8])
+def test_edge_sizes(E):
+    """Empty input, a single element (its own neighbour), one exact wave, one
+    element past a wave; faces without neighbour (-1) contribute nothing."""
+    N = 3
+    _say(f"test_edge_sizes E={E}")
+    plan = _plan(N, 0)
+    rm = refmat.refmats(N)
+    if E == 0:
+        Q = torch.zeros((0, 9, plan.B), dtype=torch.float64, device="cuda:0")
+        I = torch.zeros_like(Q)
+        tr = torch.zeros((0, 4, 9, plan.Bf), dtype=torch.float64, device="cuda:0")
+        z = lambda *s, dt=torch.float64: torch.zeros(s, dtype=dt, device="cuda:0")
+        plan.step(Q, I, tr, z(0, 9, 3, 3), z(0, 4, 9, 9), z(0, 4, 9, 9), z(0, 4, dt=torch.int32),
+                  z(0, 4, dt=torch.uint8), 0.1, 2)
+        plan.sync()
+        return
+    d = dgtest.random_stage_inputs(N, E, seed=7 + E)
+    neigh = d["neigh"].copy()
+    neigh[0, 1] = -1
+    if E > 2:
+        neigh[E - 1, 3] = -1
+    ref = stages.step(rm, 0.05, d["Q"], d["star"], d["Ap"], d["Am"], neigh, d["nface"], d["orient"])
+    Qg = _dev(d["Q"])
+    I = torch.empty(plan.dof_shape(E), dtype=torch.float64, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
+    plan.step(Qg, I, tr, plan.pack_star(_dev(d["star"])), _dev(d["Ap"]), _dev(d["Am"]), _dev(neigh),
+              _dev(d["face_rot"]), 0.05, 1)
+    assert dgtest.rel_err(_host(Qg) - d["Q"], ref - d["Q"]) <= 1e-12
+
+
+def test_step_split_equals_step():
+    """dg_step_predict + dg_step_correct is bitwise dg_step."""
+    import paper_1903_11521_amd as dg
+    N = 4
+    mesh, mats, Q, dt = dgtest.mesh_inputs(4, N, 3)
+    plan = dg.Plan(N, 0)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    args = [plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot)]
+    Qa, Qb = _dev(Q), _dev(Q)
+    I = torch.empty(plan.dof_shape(E), dtype=torch.float64, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
+    plan.step(Qa, I, tr, *args, dt, 2)
+    for _ in range(2):
+        plan.step_predict(Qb, args[0], dt, I, tr)
+        plan.step_correct(I, tr, args[0], args[1], args[2], args[3], args[4], Qb)
+    assert torch.equal(Qa, Qb)
+
+
+def test_full_size_config1_sampled():
+    """Degree 5 on the 40x40x40x6 = 384000-element mesh, one step in the launch
+    configuration the benchmark times; 96 sampled elements re-stepped by the
+    oracle (predictor on them and their neighbours)."""
+    import paper_1903_11521_amd as dg
+    N = 5
+    _say("test_full_size_config1_sampled")
+    mesh, mats, Q, dt = dgtest.mesh_inputs(40, N, 1)
+    E = mesh.E
+    plan = dg.Plan(N, 0)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    Qg = _dev(Q)
+    I = torch.empty(plan.dof_shape(E), dtype=torch.float64, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
+    plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
+              _dev(mesh.face_rot), dt, 1)
+    Q1 = _host(Qg)
+    rng = np.random.default_rng(5)
+    ids = np.sort(np.concatenate([rng.choice(E, 90, replace=False), [0, 1, 2, E - 3, E - 2, E - 1]]))
+    ostar, oAp, oAm = dgtest.oracle_element_data_subset(mesh, mats, ids)
+    ref = stages.step_subset(refmat.refmats(N), dt, ids, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface,
+                             mesh.orient)
+    assert dgtest.rel_err(Q1[ids] - Q[ids], ref - Q[ids]) <= 1e-12
