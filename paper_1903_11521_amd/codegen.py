@@ -6,11 +6,11 @@ generated code, Sec. 4.9).  This script asks the library's own host generator
 (csrc/refmat.cpp, loaded through a small host-only shared object) for the
 matrices of every supported degree and writes `dg_generated.h`:
 
-  * `__constant__` arrays holding the non-zeros of K-tilde, K-hat, R, R-hat
-    and f in the order the kernels consume them (double and float copies),
   * per-column functors that apply one column of a matrix to register arrays
-    with fully unrolled FMAs (one FMA per non-zero; the matrix entry is a
-    scalar load from the constant array at a compile-time offset).
+    with fully unrolled FMAs, one FMA per non-zero, the matrix entry written
+    as a literal of the kernel's precision.  The compiler materialises FP64
+    literals with scalar moves and folds FP32 literals into the FMA, so the
+    matrices cost neither memory traffic nor scalar-cache latency.
 
 Column order conventions (matching the consumption order of the kernels):
   KtCol<N,L>    acc[k] += Kt^d[k][L] * x_d           (predictor, d = 0..2)
@@ -60,7 +60,9 @@ def matrices(lib, N):
 
 
 def _lit(v):
-    return repr(float(v))
+    """A matrix entry as a typed literal: real(...) rounds once, at compile
+    time, to the precision of the kernel."""
+    return "real(%r)" % float(v)
 
 
 class Emitter:
@@ -109,15 +111,13 @@ def gen_degree(em, N, M):
                 for k in range(B):
                     v = A[d, k, L]
                     if v != 0.0:
-                        stm.append(f"acc[{k}] = fma(c[{len(vals)}], x{d}, acc[{k}]);")
+                        stm.append(f"acc[{k}] = fma({_lit(v)}, x{d}, acc[{k}]);")
                         vals.append(v)
             bodies.append(stm)
         cname = f"g_{key}{N}"
         add(cname, vals)
         for L in range(B):
-            em(f"template <> struct {nm}<{N}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c0, real x0, real x1, real x2, real* __restrict__ acc) {{")
-            if bodies[L]:
-                em("  const real* c = c0;")
+            em(f"template <> struct {nm}<{N}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real x0, real x1, real x2, real* __restrict__ acc) {{")
             for s in bodies[L]:
                 em("  " + s)
             em("} };")
@@ -129,9 +129,9 @@ def gen_degree(em, N, M):
             for m in range(Bf):
                 v = M["R"][S, L, m]
                 if v != 0.0:
-                    stm.append(f"tr[{m}] = fma(c[{len(vals)}], v, tr[{m}]);")
+                    stm.append(f"tr[{m}] = fma({_lit(v)}, v, tr[{m}]);")
                     vals.append(v)
-            em(f"template <> struct RCol<{N}, {S}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, real v, real* __restrict__ tr) {{")
+            em(f"template <> struct RCol<{N}, {S}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real v, real* __restrict__ tr) {{")
             for s in stm:
                 em("  " + s)
             em("} };")
@@ -144,9 +144,9 @@ def gen_degree(em, N, M):
             for k in range(B):
                 v = M["Rh"][S, k, Mi]
                 if v != 0.0:
-                    stm.append(f"acc[{k}] = fma(c[{len(vals)}], g, acc[{k}]);")
+                    stm.append(f"acc[{k}] = fma({_lit(v)}, g, acc[{k}]);")
                     vals.append(v)
-            em(f"template <> struct RhCol<{N}, {S}, {Mi}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, real g, real* __restrict__ acc) {{")
+            em(f"template <> struct RhCol<{N}, {S}, {Mi}> {{ template <typename real> __device__ __forceinline__ static void apply(real g, real* __restrict__ acc) {{")
             for s in stm:
                 em("  " + s)
             em("} };")
@@ -154,17 +154,17 @@ def gen_degree(em, N, M):
     # f^h: full apply
     for H in range(3):
         vals = []
-        em(f"template <> struct FApply<{N}, {H}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ c, const real* __restrict__ in, real* __restrict__ out) {{")
+        em(f"template <> struct FApply<{N}, {H}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ in, real* __restrict__ out) {{")
         for m in range(Bf):
             terms = [(n, M["f"][H, m, n]) for n in range(Bf) if M["f"][H, m, n] != 0.0]
             if not terms:
                 em(f"  out[{m}] = real(0);")
                 continue
             n0, v0 = terms[0]
-            em(f"  out[{m}] = c[{len(vals)}] * in[{n0}];")
+            em(f"  out[{m}] = {_lit(v0)} * in[{n0}];")
             vals.append(v0)
             for n, v in terms[1:]:
-                em(f"  out[{m}] = fma(c[{len(vals)}], in[{n}], out[{m}]);")
+                em(f"  out[{m}] = fma({_lit(v)}, in[{n}], out[{m}]);")
                 vals.append(v)
         em("} };")
         add(f"g_F{N}_{H}", vals)
@@ -202,25 +202,6 @@ def generate(host_lib_path, out_path):
     body = em.lines
     em2 = Emitter()
     em2.lines = body[:7]
-    for name, vals in allc.items():
-        n = max(1, len(vals))
-        vd = ", ".join(_lit(v) for v in vals) or "0.0"
-        em2(f"__constant__ double {name}_d[{n}] = {{{vd}}};")
-        em2(f"__constant__ float {name}_f[{n}] = {{{', '.join(_lit(np.float32(v)) + 'f' for v in vals) or '0.0f'}}};")
-    em2("template <typename real, int N> __device__ const real* gKt();")
-    em2("template <typename real, int N> __device__ const real* gKh();")
-    em2("template <typename real, int N, int S> __device__ const real* gR();")
-    em2("template <typename real, int N, int S> __device__ const real* gRh();")
-    em2("template <typename real, int N, int H> __device__ const real* gF();")
-    for tname, suf in (("double", "d"), ("float", "f")):
-        for N in DEGREES:
-            em2(f"template <> __device__ __forceinline__ const {tname}* gKt<{tname}, {N}>() {{ return g_Kt{N}_{suf}; }}")
-            em2(f"template <> __device__ __forceinline__ const {tname}* gKh<{tname}, {N}>() {{ return g_Kh{N}_{suf}; }}")
-            for S in range(4):
-                em2(f"template <> __device__ __forceinline__ const {tname}* gR<{tname}, {N}, {S}>() {{ return g_R{N}_{S}_{suf}; }}")
-                em2(f"template <> __device__ __forceinline__ const {tname}* gRh<{tname}, {N}, {S}>() {{ return g_Rh{N}_{S}_{suf}; }}")
-            for H in range(3):
-                em2(f"template <> __device__ __forceinline__ const {tname}* gF<{tname}, {N}, {H}>() {{ return g_F{N}_{H}_{suf}; }}")
     em2.lines += body[7:]
     with open(out_path + ".tmp", "w") as fh:
         fh.write("\n".join(em2.lines) + "\n")

@@ -7,8 +7,9 @@
 // never stores.  A lane owns one column (basis coefficients of quantity p)
 // of its element.  Contractions with the element-independent reference
 // matrices act column-wise and run as fully unrolled FP64/FP32 FMAs whose
-// matrix operand is a scalar-cache constant (generated from the sparsity of
-// each matrix, so structural zeros cost nothing).  Contractions over the
+// matrix operand is a compile-time literal (generated from the sparsity of
+// each matrix, so structural zeros cost nothing and the matrices need no
+// memory traffic).  Contractions over the
 // quantity index (star matrices, flux solvers) mix columns; those go through
 // a 16-row LDS chunk buffer.  All global traffic of element-major arrays is
 // staged through the same buffer so that it is fully coalesced.
@@ -194,7 +195,6 @@ __device__ __forceinline__ Star<real> load_star(const Lane<real> &L, const real 
 template <int N, bool KTILDE, int NROWS, typename real, typename Fill>
 __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<real> &S, real *acc, Fill fill)
 {
-    const real *c = KTILDE ? gKt<real, N>() : gKh<real, N>();
     static_for<0, (NROWS + CH - 1) / CH>([&](auto ci) {
         constexpr int l0 = decltype(ci)::value * CH;
         constexpr int cnt = (NROWS - l0) < CH ? (NROWS - l0) : CH;
@@ -209,8 +209,8 @@ __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<re
             const real x0 = fma(S.s[0][0], v0, fma(S.s[0][1], v1, S.s[0][2] * v2));
             const real x1 = fma(S.s[1][0], v0, fma(S.s[1][1], v1, S.s[1][2] * v2));
             const real x2 = fma(S.s[2][0], v0, fma(S.s[2][1], v1, S.s[2][2] * v2));
-            if constexpr (KTILDE) KtCol<N, l>::apply(c, x0, x1, x2, acc);
-            else KhCol<N, l>::apply(c, x0, x1, x2, acc);
+            if constexpr (KTILDE) KtCol<N, l>::apply(x0, x1, x2, acc);
+            else KhCol<N, l>::apply(x0, x1, x2, acc);
         });
         lds_sync();
     });
@@ -225,7 +225,6 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
     real a[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) a[q] = (real)A[L.p * NQ + q];
-    const real *c = gRh<real, N, S>();
     const real *xe = L.buf + L.e * NQ * LB;
     static_for<0, (Bf + CH - 1) / CH>([&](auto ci) {
         constexpr int m0 = decltype(ci)::value * CH;
@@ -237,7 +236,7 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
             real g = a[0] * xe[ri];
 #pragma unroll
             for (int q = 1; q < NQ; ++q) g = fma(a[q], xe[q * LB + ri], g);
-            RhCol<N, S, m>::apply(c, g, acc);
+            RhCol<N, S, m>::apply(g, acc);
         });
         lds_sync();
     });
@@ -247,10 +246,9 @@ template <int N, int S, typename real>
 __device__ __forceinline__ void face_trace(const real *I, real *tr)
 {
     constexpr int B = nb3(N), Bf = nb2(N);
-    const real *c = gR<real, N, S>();
 #pragma unroll
     for (int m = 0; m < Bf; ++m) tr[m] = real(0);
-    static_for<0, B>([&](auto li) { RCol<N, S, decltype(li)::value>::apply(c, I[decltype(li)::value], tr); });
+    static_for<0, B>([&](auto li) { RCol<N, S, decltype(li)::value>::apply(I[decltype(li)::value], tr); });
 }
 
 template <int N, typename real>
@@ -267,9 +265,9 @@ __device__ __forceinline__ void face_trace_rt(int j, const real *I, real *tr)
 template <int N, typename real>
 __device__ __forceinline__ void orient_rt(int h, const real *in, real *out)
 {
-    if (h == 0) FApply<N, 0>::apply(gF<real, N, 0>(), in, out);
-    else if (h == 1) FApply<N, 1>::apply(gF<real, N, 1>(), in, out);
-    else FApply<N, 2>::apply(gF<real, N, 2>(), in, out);
+    if (h == 0) FApply<N, 0>::apply(in, out);
+    else if (h == 1) FApply<N, 1>::apply(in, out);
+    else FApply<N, 2>::apply(in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +394,6 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
     auto icol = [&](int c) -> const real * { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
     static_for<0, 4>([&](auto si) {
         constexpr int S = decltype(si)::value;
-        const real *cr = gR<real, N, S>();
 #pragma unroll
         for (int m = 0; m < Bf; ++m) tr[m] = real(0);
         static_for<0, (B + CH - 1) / CH>([&](auto ci) {
@@ -404,7 +401,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
             constexpr int cnt = (B - l0) < CH ? (B - l0) : CH;
             chunk_load<cnt, real, real>(L, icol, l0);
             lds_sync();
-            static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(cr, L.own[ri], tr); });
+            static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(L.own[ri], tr); });
             lds_sync();
         });
         flux_lift<N, S>(L, Ap + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
