@@ -35,11 +35,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "mixed"], default="fp64")
     ap.add_argument("--degree", type=int, default=5)
     ap.add_argument("--n", type=int, default=40, help="cubes per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", choices=["single", "batched"], default="single",
+                    help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree")
+    ap.add_argument("--meshes", type=int, default=32)
     return ap.parse_args()
 
 
@@ -96,19 +99,88 @@ def cpu_baseline(args, mesh, mats, Q, dt):
                       "FP64 dense loop nests, OpenMP over elements; %.1f s" % (S, mesh.E, args.degree, t)}
 
 
+def batched(args):
+    """32 independent cube-split meshes, E_i ~ log-uniform[10k, 200k] elements
+    (n_i = round((E_i/6)^(1/3)) cubes per direction), degree U{2..6}, random
+    materials and N(0,1) DOFs per mesh; all stepped together (one predictor and
+    one corrector launch per degree, recorded once in a HIP graph)."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
+    rng = np.random.Generator(np.random.PCG64(seed_for(2)))
+    sizes = np.exp(rng.uniform(np.log(10e3), np.log(200e3), args.meshes))
+    degrees = rng.integers(2, 7, args.meshes)
+    dev = torch.device("cuda:0")
+    meshes, flops, nbytes = [], 0.0, 0.0
+    fms = {N: dg.flop_model(N) for N in range(2, 7)}
+    for i, (Ei, N) in enumerate(zip(sizes, degrees)):
+        n = max(3, int(round((Ei / 6) ** (1 / 3))))
+        seed = seed_for(2) + 1000 * (i + 1)
+        mesh = cube_mesh(n, seed)
+        E = mesh.E
+        plan = dg.Plan(int(N), prec)
+        mats = random_materials(E, seed)
+        Q = random_dofs(E, 9, plan.B, seed)
+        star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        meshes.append(dict(degree=int(N), E=E, dt=dt_from_mesh(mesh, mats), Q=t(Q).to(plan.dtype),
+                           I=torch.empty(plan.dof_shape(E), dtype=plan.dtype, device=dev),
+                           traces=torch.empty(plan.trace_shape(E), dtype=plan.dtype, device=dev),
+                           star_packed=plan.pack_star(t(star)), Aplus=t(Ap), Aminus=t(Am),
+                           neigh=t(mesh.neigh), face_rot=t(mesh.face_rot)))
+        itemsize = 8 if prec == dg.DG_FP64 else 4
+        flops += fms[int(N)]["step"] * E
+        nbytes += dg.byte_model(int(N), itemsize)["step"] * E
+        del star, Ap, Am
+    total = sum(m["E"] for m in meshes)
+    log("batch of %d meshes, %d elements, degrees %s" % (len(meshes), total, sorted(set(degrees.tolist()))))
+    batch = dg.Batch(prec, meshes)
+    torch.cuda.synchronize()
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ridge = 78.6e12 / 8e12
+    if flops / nbytes < ridge:
+        roof = {"bound": "hbm", "achieved": nbytes * args.steps / el / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops * args.steps / el / 1e12, "peak": 78.6, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "whole batched step (all launches of one graph replay)"
+    out = {"metric": "element-updates/s", "value": total * args.steps / el, "unit": "element-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
+           "data": "synthetic",
+           "config": {"workload": "batched: %d independent elastic cube-split meshes, %d elements in total, "
+                                  "log-uniform 10k-200k elements per mesh, degrees uniform in 2..6, one HIP graph "
+                                  "replay per step" % (len(meshes), total),
+                      "elements": total, "degrees": degrees.tolist(), "mesh_elements": [m["E"] for m in meshes]},
+           "useful_gflops": flops * args.steps / el / 1e9, "roofline": roof}
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
                           "note (DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "batched":
+        return batched(args)
     import torch
 
     import paper_1903_11521_amd as dg
     from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
 
     N = args.degree
-    prec = dg.DG_FP64 if args.precision == "fp64" else dg.DG_FP32
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
     plan = dg.Plan(N, prec)
     seed = seed_for(1)
     log("building mesh n=%d degree=%d" % (args.n, N))
@@ -179,7 +251,8 @@ def main():
         "metric": "element-updates/s", "value": value, "unit": "element-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == dg.DG_FP64 else "f32", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": "elastic ADER-DG, degree %d (B=%d), %dx%dx%dx6 = %d-element jittered periodic "
                                "cube-split mesh, random materials, %d time steps" % (N, plan.B, args.n, args.n,
                                                                                      args.n, E, args.steps),

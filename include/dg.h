@@ -38,7 +38,7 @@
  *                                  face's first vertex in the neighbour's
  *                                  face triple)
  *   The element type of DOF arrays is double for DG_FP64 plans and float for
- *   DG_FP32 plans.
+ *   DG_FP32 and DG_MIXED plans.
  *
  * Memory and streams: every array argument of the dg_* compute calls is a
  * DEVICE pointer owned by the caller; the library does not allocate, free or
@@ -65,7 +65,12 @@ extern "C" {
 
 typedef struct dg_plan dg_plan;
 
-typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
+/* DG_FP64: everything in FP64.  DG_FP32: DOFs, star matrices and every
+ * contraction in FP32 (flux solvers are read as FP64 and rounded).
+ * DG_MIXED: FP32 DOFs and reference-matrix contractions; the Taylor time
+ * integral is accumulated in FP64 and the flux-solver products run in FP64
+ * (rounded once to FP32).  DOF-like arrays are float for FP32 and MIXED. */
+typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 2 } dg_precision;
 
 typedef enum {
     DG_OK = 0,
@@ -157,6 +162,35 @@ int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, co
 int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *traces,
                     const void *star_packed, const double *Aplus, const double *Aminus,
                     const int32_t *neigh, const uint8_t *face_rot, void *Q, hipStream_t stream);
+
+/* ---- batches of independent meshes (mixed degrees) --------------------- */
+
+/* One mesh of a batch.  All pointers are device pointers owned by the caller
+ * and must stay valid for the batch's lifetime; layouts as for dg_step with
+ * the item's degree; element type per the batch precision. */
+typedef struct {
+    int degree;                 /* 2..6 */
+    int64_t E;                  /* elements of this mesh (>= 0) */
+    double dt;                  /* time step of this mesh */
+    void *Q, *I, *traces;       /* DOFs (updated in place) and work arrays */
+    const void *star_packed;
+    const double *Aplus, *Aminus;
+    const int32_t *neigh;       /* indices local to this mesh, in [0, E) */
+    const uint8_t *face_rot;
+} dg_batch_item;
+
+typedef struct dg_batch dg_batch;
+
+/* Builds the work tables of a batch (device memory owned by the batch; this
+ * call allocates and copies synchronously).  One time step of a batch is one
+ * predictor launch and one corrector launch per degree present, over all
+ * meshes of that degree; the launches of a step are recorded once into a HIP
+ * graph and replayed.  Each element's arithmetic is identical to dg_step's,
+ * so a mesh gives bitwise the same result alone and in any batch. */
+int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out);
+/* n_steps time steps of every mesh of the batch, stream ordered. */
+int dg_batch_step(dg_batch *batch, int n_steps, hipStream_t stream);
+int dg_batch_destroy(dg_batch *batch);
 
 /* Waits for the stream; reports asynchronous kernel failures as DG_EHIP. */
 int dg_sync(hipStream_t stream);

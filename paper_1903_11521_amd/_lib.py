@@ -10,6 +10,15 @@ import numpy as np
 
 DG_FP64 = 0
 DG_FP32 = 1
+DG_MIXED = 2
+
+
+class BatchItem(ctypes.Structure):
+    """dg_batch_item of include/dg.h."""
+    _fields_ = [("degree", ctypes.c_int), ("E", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("Q", ctypes.c_void_p), ("I", ctypes.c_void_p), ("traces", ctypes.c_void_p),
+                ("star_packed", ctypes.c_void_p), ("Aplus", ctypes.c_void_p), ("Aminus", ctypes.c_void_p),
+                ("neigh", ctypes.c_void_p), ("face_rot", ctypes.c_void_p)]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libdg_mi355x.so"
@@ -55,6 +64,9 @@ def _load():
         lib.dg_step_predict.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp]
         lib.dg_step_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_sync.argtypes = [vp]
+        lib.dg_batch_create.argtypes = [i32, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(vp)]
+        lib.dg_batch_step.argtypes = [vp, i32, vp]
+        lib.dg_batch_destroy.argtypes = [vp]
         _lib = lib
         return lib
 
@@ -183,6 +195,19 @@ class Plan:
             self._h = None
 
     # -- argument helpers ----------------------------------------------------
+    @staticmethod
+    def _check_tensor(t, shape, dtype, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+        if t.dtype != dtype:
+            raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+        if t.numel() and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous device tensor" % name)
+        return t.data_ptr() if t.numel() else None
+
     def _t(self, t, shape, dtype, name):
         torch = _torch()
         if not isinstance(t, torch.Tensor):
@@ -303,3 +328,47 @@ class Plan:
     @staticmethod
     def sync(stream=None):
         _check(_load().dg_sync(Plan._stream(stream)))
+
+
+class Batch:
+    """A batch of independent meshes (any degrees) stepped together: one
+    predictor and one corrector launch per degree present, replayed as a HIP
+    graph.  `meshes` is a list of dicts with keys degree, E, dt, Q, I, traces,
+    star_packed, Aplus, Aminus, neigh, face_rot (device tensors owned by the
+    caller and kept alive by this object)."""
+
+    def __init__(self, precision, meshes):
+        lib = _load()
+        torch = _torch()
+        self.precision = precision
+        dt_ = torch.float64 if precision == DG_FP64 else torch.float32
+        arr = (BatchItem * max(1, len(meshes)))()
+        self._keep = []
+        for i, m in enumerate(meshes):
+            N, E = int(m["degree"]), int(m["E"])
+            B, Bf = comb(N + 3, 3), comb(N + 2, 2)
+            chk = Plan._check_tensor
+            arr[i] = BatchItem(N, E, float(m["dt"]),
+                               chk(m["Q"], (E, 9, B), dt_, "Q"), chk(m["I"], (E, 9, B), dt_, "I"),
+                               chk(m["traces"], (E, 4, 9, Bf), dt_, "traces"),
+                               chk(m["star_packed"], (E, 9, 3, 3), dt_, "star_packed"),
+                               chk(m["Aplus"], (E, 4, 9, 9), torch.float64, "Aplus"),
+                               chk(m["Aminus"], (E, 4, 9, 9), torch.float64, "Aminus"),
+                               chk(m["neigh"], (E, 4), torch.int32, "neigh"),
+                               chk(m["face_rot"], (E, 4), torch.uint8, "face_rot"))
+            self._keep.append(m)
+        h = ctypes.c_void_p()
+        _check(lib.dg_batch_create(precision, arr, len(meshes), ctypes.byref(h)))
+        self._h = h
+        self.elements = sum(int(m["E"]) for m in meshes)
+
+    def step(self, n_steps=1, stream=None):
+        _check(_load().dg_batch_step(self._h, int(n_steps), Plan._stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.dg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -6,9 +6,11 @@
 
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "dg_internal.h"
 #include "refmat.h"
@@ -42,16 +44,15 @@ int hip_status(hipError_t e, const char *where)
 }
 
 struct Tables {
-    DgTable t64[7], t32[7];
+    DgTable t[3][7];   // [precision][degree]
     Tables()
     {
-        std::memset(t64, 0, sizeof t64);
-        std::memset(t32, 0, sizeof t32);
-        dg_table_2(&t64[2], &t32[2]);
-        dg_table_3(&t64[3], &t32[3]);
-        dg_table_4(&t64[4], &t32[4]);
-        dg_table_5(&t64[5], &t32[5]);
-        dg_table_6(&t64[6], &t32[6]);
+        std::memset(t, 0, sizeof t);
+        dg_table_2(&t[0][2], &t[1][2], &t[2][2]);
+        dg_table_3(&t[0][3], &t[1][3], &t[2][3]);
+        dg_table_4(&t[0][4], &t[1][4], &t[2][4]);
+        dg_table_5(&t[0][5], &t[1][5], &t[2][5]);
+        dg_table_6(&t[0][6], &t[1][6], &t[2][6]);
     }
 };
 
@@ -62,6 +63,24 @@ const Tables &tables()
 }
 
 bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+DgItem make_item(int64_t E, double dt, void *Q, void *I, void *traces, const void *star, const double *Ap,
+                 const double *Am, const int32_t *neigh, const uint8_t *fr)
+{
+    DgItem it;
+    it.E = E;
+    it.dt = dt;
+    it.Q = Q;
+    it.I = I;
+    it.traces = traces;
+    it.star = star;
+    it.Ap = Ap;
+    it.Am = Am;
+    it.neigh = neigh;
+    it.face_rot = fr;
+    it.first_block = 0;
+    return it;
+}
 
 #define CHECK_PLAN(pl)                                                              \
     do {                                                                            \
@@ -102,7 +121,7 @@ int dg_plan_create(int degree, dg_precision precision, dg_plan **out)
     if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
     *out = nullptr;
     if (degree < 2 || degree > 6) return fail(DG_EUNSUPPORTED, "degree %s%lld outside 2..6", "", degree);
-    if (precision != DG_FP64 && precision != DG_FP32)
+    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
         return fail(DG_EUNSUPPORTED, "unsupported precision %s%lld", "", (long long)precision);
     dg_plan *p = new (std::nothrow) dg_plan;
     if (!p) return fail(DG_ENOMEM, "out of host memory%s", "");
@@ -110,7 +129,7 @@ int dg_plan_create(int degree, dg_precision precision, dg_plan **out)
     p->prec = precision;
     p->B = dgref::basis_size(degree);
     p->Bf = dgref::face_basis_size(degree);
-    p->tab = precision == DG_FP64 ? tables().t64[degree] : tables().t32[degree];
+    p->tab = tables().t[precision][degree];
     *out = p;
     return DG_OK;
 }
@@ -208,10 +227,11 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
+    const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
     for (int n = 0; n < n_steps; ++n) {
-        hipError_t e = plan->tab.step_predict(E, dt, Q, star_packed, I, traces, s);
+        hipError_t e = plan->tab.step_predict(it, s);
         if (e != hipSuccess) return hip_status(e, "dg_step (predict)");
-        e = plan->tab.step_correct(E, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, Q, s);
+        e = plan->tab.step_correct(it, s);
         if (e != hipSuccess) return hip_status(e, "dg_step (correct)");
     }
     return DG_OK;
@@ -226,7 +246,9 @@ int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, co
     CHECK_PTR(E, star_packed, "star_packed");
     CHECK_PTR(E, I, "I");
     CHECK_PTR(E, traces, "traces");
-    return hip_status(plan->tab.step_predict(E, dt, Q, star_packed, I, traces, s), "dg_step_predict");
+    const DgItem it = make_item(E, dt, const_cast<void *>(Q), I, traces, star_packed, nullptr, nullptr, nullptr,
+                                nullptr);
+    return hip_status(plan->tab.step_predict(it, s), "dg_step_predict");
 }
 
 int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *traces, const void *star_packed,
@@ -243,8 +265,140 @@ int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *t
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
     CHECK_PTR(E, Q, "Q");
-    return hip_status(plan->tab.step_correct(E, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, Q, s),
-                      "dg_step_correct");
+    const DgItem it = make_item(E, 0.0, Q, const_cast<void *>(I), const_cast<void *>(traces), star_packed, Aplus,
+                                Aminus, neigh, face_rot);
+    return hip_status(plan->tab.step_correct(it, s), "dg_step_correct");
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct dg_batch {
+    struct Group {
+        int degree = 0;
+        DgTable tab{};
+        DgItem *d_items = nullptr;
+        int32_t *d_block_item = nullptr;
+        int64_t nblocks = 0;
+    };
+    dg_precision prec = DG_FP64;
+    std::vector<Group> groups;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;
+    ~dg_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (capture) (void)hipStreamDestroy(capture);
+        for (auto &g : groups) {
+            if (g.d_items) (void)hipFree(g.d_items);
+            if (g.d_block_item) (void)hipFree(g.d_block_item);
+        }
+    }
+};
+
+extern "C" {
+
+int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out)
+{
+    if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
+    *out = nullptr;
+    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
+        return fail(DG_EUNSUPPORTED, "unsupported precision %s%lld", "", (long long)precision);
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(DG_EINVAL, "bad item list%s", "");
+    for (int i = 0; i < n_items; ++i) {
+        const dg_batch_item &x = items[i];
+        if (x.degree < 2 || x.degree > 6) return fail(DG_EUNSUPPORTED, "item degree %s%lld outside 2..6", "", x.degree);
+        CHECK_E(x.E);
+        CHECK_PTR(x.E, x.Q, "item Q");
+        CHECK_PTR(x.E, x.I, "item I");
+        CHECK_PTR(x.E, x.traces, "item traces");
+        CHECK_PTR(x.E, x.star_packed, "item star_packed");
+        CHECK_PTR(x.E, x.Aplus, "item Aplus");
+        CHECK_PTR(x.E, x.Aminus, "item Aminus");
+        CHECK_PTR(x.E, x.neigh, "item neigh");
+        CHECK_PTR(x.E, x.face_rot, "item face_rot");
+    }
+    std::unique_ptr<dg_batch> b(new (std::nothrow) dg_batch);
+    if (!b) return fail(DG_ENOMEM, "out of host memory%s", "");
+    b->prec = precision;
+    for (int deg = 2; deg <= 6; ++deg) {
+        std::vector<DgItem> hv;
+        std::vector<int32_t> bi;
+        int64_t nb = 0;
+        for (int i = 0; i < n_items; ++i) {
+            const dg_batch_item &x = items[i];
+            if (x.degree != deg || x.E == 0) continue;
+            DgItem it = make_item(x.E, x.dt, x.Q, x.I, x.traces, x.star_packed, x.Aplus, x.Aminus, x.neigh,
+                                  x.face_rot);
+            it.first_block = nb;
+            const int64_t blocks = (x.E + DG_ELEMENTS_PER_BLOCK - 1) / DG_ELEMENTS_PER_BLOCK;
+            for (int64_t k = 0; k < blocks; ++k) bi.push_back((int32_t)hv.size());
+            nb += blocks;
+            hv.push_back(it);
+        }
+        if (hv.empty()) continue;
+        if (nb > 0x7fffffff) return fail(DG_EINVAL, "batch too large%s", "");
+        dg_batch::Group g;
+        g.degree = deg;
+        g.tab = tables().t[precision][deg];
+        g.nblocks = nb;
+        b->groups.push_back(g);
+        dg_batch::Group &G = b->groups.back();
+        hipError_t e = hipMalloc(&G.d_items, sizeof(DgItem) * hv.size());
+        if (e == hipSuccess) e = hipMalloc(&G.d_block_item, sizeof(int32_t) * bi.size());
+        if (e == hipSuccess) e = hipMemcpy(G.d_items, hv.data(), sizeof(DgItem) * hv.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(G.d_block_item, bi.data(), sizeof(int32_t) * bi.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_status(e, "dg_batch_create");
+    }
+    *out = b.release();
+    return DG_OK;
+}
+
+static hipError_t batch_enqueue(dg_batch *b, hipStream_t s)
+{
+    for (auto &g : b->groups) {
+        hipError_t e = g.tab.batch_predict(g.d_items, g.d_block_item, g.nblocks, s);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &g : b->groups) {
+        hipError_t e = g.tab.batch_correct(g.d_items, g.d_block_item, g.nblocks, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int dg_batch_step(dg_batch *b, int n_steps, hipStream_t s)
+{
+    if (!b) return fail(DG_EINVAL, "null batch%s", "");
+    if (n_steps < 0) return fail(DG_EINVAL, "negative step count%s %lld", "", n_steps);
+    if (n_steps == 0 || b->groups.empty()) return DG_OK;
+    if (!b->exec) {
+        // record one step into a graph on a private stream, then replay it
+        hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_status(e, "dg_batch_step (capture)");
+        hipError_t le = batch_enqueue(b, b->capture);
+        e = hipStreamEndCapture(b->capture, &b->graph);
+        if (le != hipSuccess) return hip_status(le, "dg_batch_step (launch)");
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_status(e, "dg_batch_step (instantiate)");
+    }
+    for (int n = 0; n < n_steps; ++n) {
+        hipError_t e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) return hip_status(e, "dg_batch_step");
+    }
+    return DG_OK;
+}
+
+int dg_batch_destroy(dg_batch *b)
+{
+    delete b;
+    return DG_OK;
 }
 
 int dg_sync(hipStream_t s) { return hip_status(hipStreamSynchronize(s), "dg_sync"); }

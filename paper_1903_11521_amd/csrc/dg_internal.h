@@ -4,6 +4,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Host image of one mesh of a (batched) time step; layout identical to the
+// kernels' StepItem<real>.
+struct DgItem {
+    int64_t E;
+    double dt;
+    void *Q, *I, *traces;
+    const void *star;
+    const double *Ap, *Am;
+    const int32_t *neigh;
+    const uint8_t *face_rot;
+    int64_t first_block;
+};
+
+constexpr int DG_ELEMENTS_PER_BLOCK = 7;
+
 struct DgTable {
     hipError_t (*pack_star)(int64_t E, const double *dense, void *packed, hipStream_t s);
     hipError_t (*predictor)(int64_t E, double dt, const void *Q, const void *star, void *T, hipStream_t s);
@@ -12,15 +27,17 @@ struct DgTable {
     hipError_t (*local_flux)(int64_t E, const void *I, const double *Ap, void *Q, hipStream_t s);
     hipError_t (*neighbour_flux)(int64_t E, int64_t nI, const void *I, const int32_t *neigh, const uint8_t *fr,
                                  const double *Am, void *Q, hipStream_t s);
-    hipError_t (*step_predict)(int64_t E, double dt, const void *Q, const void *star, void *I, void *traces,
-                               hipStream_t s);
-    hipError_t (*step_correct)(int64_t E, const void *I, const void *traces, const void *star, const double *Ap,
-                               const double *Am, const int32_t *neigh, const uint8_t *fr, void *Q,
-                               hipStream_t s);
+    hipError_t (*step_predict)(const DgItem &it, hipStream_t s);
+    hipError_t (*step_correct)(const DgItem &it, hipStream_t s);
+    // batched: items (device array) of one degree; block_item maps each of the
+    // nblocks workgroups to its item
+    hipError_t (*batch_predict)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);
+    hipError_t (*batch_correct)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);
 };
 
-void dg_table_2(DgTable *fp64, DgTable *fp32);
-void dg_table_3(DgTable *fp64, DgTable *fp32);
-void dg_table_4(DgTable *fp64, DgTable *fp32);
-void dg_table_5(DgTable *fp64, DgTable *fp32);
-void dg_table_6(DgTable *fp64, DgTable *fp32);
+// tables for DG_FP64, DG_FP32 and DG_MIXED
+void dg_table_2(DgTable *fp64, DgTable *fp32, DgTable *mixed);
+void dg_table_3(DgTable *fp64, DgTable *fp32, DgTable *mixed);
+void dg_table_4(DgTable *fp64, DgTable *fp32, DgTable *mixed);
+void dg_table_5(DgTable *fp64, DgTable *fp32, DgTable *mixed);
+void dg_table_6(DgTable *fp64, DgTable *fp32, DgTable *mixed);

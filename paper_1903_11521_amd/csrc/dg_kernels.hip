@@ -69,17 +69,23 @@ struct Lane {
     real *own;      // this lane's column in buf
 };
 
+// XCD-aware block order: the hardware deals consecutive workgroups round
+// robin to the 8 XCDs; remapping makes each XCD (own L2) walk a contiguous
+// range of elements, which keeps face neighbours in the same L2.
+__device__ __forceinline__ int64_t logical_block()
+{
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t full = (nb >> 3) << 3;
+    return b < full ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
 template <typename real>
-__device__ __forceinline__ Lane<real> make_lane(real *buf, int64_t E)
+__device__ __forceinline__ Lane<real> make_lane(real *buf, int64_t E, int64_t lb)
 {
     Lane<real> L;
     L.lane = threadIdx.x;
     L.e = L.lane / NQ;
     L.p = L.lane - L.e * NQ;
-    // XCD-aware block order: consecutive element ranges stay on one XCD
-    const int64_t nb = gridDim.x, b = blockIdx.x;
-    const int64_t full = (nb >> 3) << 3;
-    const int64_t lb = b < full ? (b & 7) * (nb >> 3) + (b >> 3) : b;
     L.base = lb * EPW;
     const int64_t el = L.base + L.e;
     L.active = (L.e < EPW) && (el < E);
@@ -218,13 +224,16 @@ __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<re
 
 // acc[k] += sum_m Rh^S[k][m] sum_q A[p][q] X[m][q] for face rows m in [0,Bf)
 // with X chunk-wise in LDS (fill brings rows in).
-template <int N, int S, typename real, typename Fill>
+template <int N, int S, bool MIX = false, typename real, typename Fill>
 __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, real *acc, Fill fill)
 {
+    // MIX: the flux-solver product runs in FP64 (FP64 matrices, FP32 traces),
+    // rounded once before the FP32 lift
+    using mreal = typename std::conditional<MIX, double, real>::type;
     constexpr int Bf = nb2(N);
-    real a[NQ];
+    mreal a[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) a[q] = (real)A[L.p * NQ + q];
+    for (int q = 0; q < NQ; ++q) a[q] = (mreal)A[L.p * NQ + q];
     const real *xe = L.buf + L.e * NQ * LB;
     static_for<0, (Bf + CH - 1) / CH>([&](auto ci) {
         constexpr int m0 = decltype(ci)::value * CH;
@@ -233,10 +242,10 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
         lds_sync();
         static_for<0, cnt>([&](auto ri) {
             constexpr int m = m0 + decltype(ri)::value;
-            real g = a[0] * xe[ri];
+            mreal g = a[0] * (mreal)xe[ri];
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) g = fma(a[q], xe[q * LB + ri], g);
-            RhCol<N, S, m>::apply(g, acc);
+            for (int q = 1; q < NQ; ++q) g = fma(a[q], (mreal)xe[q * LB + ri], g);
+            RhCol<N, S, m>::apply((real)g, acc);
         });
         lds_sync();
     });
@@ -275,9 +284,11 @@ __device__ __forceinline__ void orient_rt(int h, const real *in, real *out)
 // seissol:timeint) accumulated on the fly.  T^0 = Q,
 // T^{d+1} = dt/(d+1) sum_xi Kt^xi T^d star^xi^T,  I = sum_d dt/(d+1) T^d.
 // ---------------------------------------------------------------------------
-template <int N, int D, bool WRITE_T, bool ACC_I, typename real, typename TColPtr>
-__device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real> &S, real dt, real *src,
-                                           real *I, TColPtr tcol, int64_t E)
+// ireal: type of the time-integral accumulator (FP64 in the mixed form).
+// ALIAS: src and I are the same array (T^0 = Q accumulates into I in place).
+template <int N, int D, bool WRITE_T, bool ACC_I, bool ALIAS, typename real, typename ireal, typename TColPtr>
+__device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real> &S, ireal dt, real *src,
+                                           ireal *I, TColPtr tcol, int64_t E)
 {
     constexpr int B = nb3(N);
     if constexpr (D < N) {
@@ -291,16 +302,20 @@ __device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real>
         });
         if constexpr (ACC_I && D == 0) {
 #pragma unroll
-            for (int k = 0; k < B; ++k) I[k] *= dt;     // src aliases I: T^0 = Q
+            for (int k = 0; k < B; ++k) {
+                if constexpr (ALIAS) I[k] *= dt;          // src aliases I: T^0 = Q
+                else I[k] = dt * (ireal)src[k];
+            }
         }
-        const real sc = dt / real(D + 1), si = dt / real(D + 2);
+        const real sc = real(dt / ireal(D + 1));
+        const ireal si = dt / ireal(D + 2);
 #pragma unroll
         for (int k = 0; k < bout; ++k) {
             acc[k] *= sc;
-            if constexpr (ACC_I) I[k] = fma(si, acc[k], I[k]);
+            if constexpr (ACC_I) I[k] = fma(si, (ireal)acc[k], I[k]);
         }
         if constexpr (WRITE_T) store_columns<B, bout>(L, [&](int c) { return tcol(c, D + 1); }, acc, E);
-        ck_recurse<N, D + 1, WRITE_T, ACC_I>(L, S, dt, acc, I, tcol, E);
+        ck_recurse<N, D + 1, WRITE_T, ACC_I, ALIAS>(L, S, dt, acc, I, tcol, E);
     }
 }
 
@@ -313,7 +328,7 @@ __global__ void __launch_bounds__(64) k_derivative(int64_t E, real dt, const rea
 {
     constexpr int B = nb3(N), bin = nb3(N - D), bout = nb3(N - D - 1);
     __shared__ real buf[NCOL * LB];
-    const Lane<real> L = make_lane(buf, E);
+    const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
     auto tcol = [&](int c, int d) { return T + ((slot_elem(L.base, c, E) * (N + 1) + d) * NQ + c % NQ) * B; };
     real acc[bout];
@@ -370,7 +385,7 @@ __global__ void __launch_bounds__(64) k_volume(int64_t E, const real *__restrict
 {
     constexpr int B = nb3(N);
     __shared__ real buf[NCOL * LB];
-    const Lane<real> L = make_lane(buf, E);
+    const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
     real acc[B];
 #pragma unroll
@@ -381,13 +396,13 @@ __global__ void __launch_bounds__(64) k_volume(int64_t E, const real *__restrict
 
 // Local flux: Q += sum_S Rh^S (R^S^T I) A+^S^T   (per-stage form: the trace
 // of each face is accumulated from I rows streamed through LDS)
-template <int N, typename real>
+template <int N, bool MIX, typename real>
 __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__restrict__ I, const double *__restrict__ Ap,
                                                    real *__restrict__ Q)
 {
     constexpr int B = nb3(N), Bf = nb2(N);
     __shared__ real buf[NCOL * LB];
-    const Lane<real> L = make_lane(buf, E);
+    const Lane<real> L = make_lane(buf, E, logical_block());
     real acc[B], tr[Bf];
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = real(0);
@@ -404,7 +419,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
             static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(L.own[ri], tr); });
             lds_sync();
         });
-        flux_lift<N, S>(L, Ap + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
+        flux_lift<N, S, MIX>(L, Ap + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
             constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
             static_for<0, cnt>([&](auto ri) { L.own[ri] = tr[m0 + ri]; });
         });
@@ -413,7 +428,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
 }
 
 // Neighbour flux: Q += sum_S Rh^S f^h (R^j^T I^nu) A-^S^T  (per-stage form)
-template <int N, typename real>
+template <int N, bool MIX, typename real>
 __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, const real *__restrict__ I,
                                                        const int32_t *__restrict__ neigh,
                                                        const uint8_t *__restrict__ face_rot,
@@ -422,7 +437,7 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
     constexpr int B = nb3(N), Bf = nb2(N);
     __shared__ real buf[NCOL * LB];
     __shared__ int nbt[8][4];
-    const Lane<real> L = make_lane(buf, E);
+    const Lane<real> L = make_lane(buf, E, logical_block());
     if (L.p == 0) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -448,7 +463,7 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
 #pragma unroll
             for (int m = 0; m < Bf; ++m) t2[m] = real(0);
         }
-        flux_lift<N, S>(L, Am + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
+        flux_lift<N, S, MIX>(L, Am + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
             constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
             static_for<0, cnt>([&](auto ri) { L.own[ri] = t2[m0 + ri]; });
         });
@@ -457,80 +472,71 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
 }
 
 // ---------------------------------------------------------------------------
-// Time step, part 1: predictor + time integral + face traces of I.
+// Time step.  One mesh of a step is described by a StepItem; the same device
+// bodies serve a single mesh (one item) and a batch of meshes (a block-to-item
+// table selects the item of each workgroup).
 // ---------------------------------------------------------------------------
-template <int N, typename real>
-__global__ void __launch_bounds__(64) k_step_predict(int64_t E, real dt, const real *__restrict__ Q,
-                                                     const real *__restrict__ star, real *__restrict__ I,
-                                                     real *__restrict__ traces)
+template <typename real>
+struct StepItem {
+    int64_t E;
+    double dt;
+    real *Q, *I, *traces;
+    const real *star;
+    const double *Ap, *Am;
+    const int32_t *neigh;
+    const uint8_t *face_rot;
+    int64_t first_block;     // first workgroup of this item in a batched launch
+};
+
+// part 1: predictor + time integral (+ FP64 accumulation in the mixed form)
+// + face traces of I;  part 2: volume + local flux + neighbour flux -> Q.
+template <int N, bool MIX, typename real>
+__global__ void __launch_bounds__(64)
+k_step_predict(int64_t E, double dt, const real *__restrict__ Q, const real *__restrict__ star,
+               real *__restrict__ Iout, real *__restrict__ traces)
 {
-    constexpr int B = nb3(N), Bf = nb2(N);
-    __shared__ real buf[NCOL * LB];
-    const Lane<real> L = make_lane(buf, E);
-    const Star<real> S = load_star(L, star);
-    real Ic[B];
-    load_columns<B, real, real>(L, [&](int c) -> const real * { return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, Ic);
-    auto nocol = [](int, int) { return (real *)nullptr; };
-    ck_recurse<N, 0, false, true>(L, S, dt, Ic, Ic, nocol, E);
-    store_columns<B, B>(L, [&](int c) { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, Ic, E);
-    real tr[Bf];
-    static_for<0, 4>([&](auto si) {
-        constexpr int Sf = decltype(si)::value;
-        face_trace<N, Sf>(Ic, tr);
-        store_columns<Bf, Bf>(L, [&](int c) { return traces + ((slot_elem(L.base, c, E) * 4 + Sf) * NQ + c % NQ) * Bf; }, tr, E);
-    });
+    const int64_t lb = logical_block();
+#include "step_predict_body.inc"
 }
 
-// Time step, part 2: volume + local flux + neighbour flux -> Q.
-template <int N, typename real>
-__global__ void __launch_bounds__(64) k_step_correct(int64_t E, const real *__restrict__ I,
-                                                     const real *__restrict__ traces, const real *__restrict__ star,
-                                                     const double *__restrict__ Ap, const double *__restrict__ Am,
-                                                     const int32_t *__restrict__ neigh,
-                                                     const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
+template <int N, bool MIX, typename real>
+__global__ void __launch_bounds__(64)
+k_step_correct(int64_t E, const real *__restrict__ Iin, const real *__restrict__ traces,
+               const real *__restrict__ star, const double *__restrict__ Ap, const double *__restrict__ Am,
+               const int32_t *__restrict__ neigh, const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
 {
-    constexpr int B = nb3(N), Bf = nb2(N);
-    __shared__ real buf[NCOL * LB];
-    __shared__ int nbt[8][4];
-    __shared__ int jt[8][4];
-    const Lane<real> L = make_lane(buf, E);
-    if (L.p == 0) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int nu = neigh[L.elem * 4 + s];
-            nbt[L.e][s] = (nu >= 0 && nu < E) ? nu : -1;    // out of range: no neighbour
-            jt[L.e][s] = face_rot[L.elem * 4 + s] & 3;
-        }
-    }
-    lds_sync();
-    const Star<real> S = load_star(L, star);
-    real acc[B];
-#pragma unroll
-    for (int k = 0; k < B; ++k) acc[k] = real(0);
-    volume_acc<N>(L, S, I, acc, E);
-    static_for<0, 4>([&](auto si) {
-        constexpr int Sf = decltype(si)::value;
-        flux_lift<N, Sf>(L, Ap + (L.elem * 4 + Sf) * 81, acc, [&](auto m0c, auto cntc) {
-            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
-            chunk_load<cnt, real, real>(L, [&](int c) -> const real * {
-                return traces + ((slot_elem(L.base, c, E) * 4 + Sf) * NQ + c % NQ) * Bf; }, m0);
-        });
-    });
-    real tn[Bf], t2[Bf];
-    static_for<0, 4>([&](auto si) {
-        constexpr int Sf = decltype(si)::value;
-        load_columns<Bf, real, real>(L, [&](int c) -> const real * {
-            const int nu = nbt[c / NQ][Sf];
-            return nu >= 0 ? traces + (((int64_t)nu * 4 + jt[c / NQ][Sf]) * NQ + c % NQ) * Bf : nullptr;
-        }, tn);
-        const uint8_t fr = face_rot[L.elem * 4 + Sf];
-        orient_rt<N>(fr >> 2, tn, t2);
-        flux_lift<N, Sf>(L, Am + (L.elem * 4 + Sf) * 81, acc, [&](auto m0c, auto cntc) {
-            constexpr int m0 = decltype(m0c)::value, cnt = decltype(cntc)::value;
-            static_for<0, cnt>([&](auto ri) { L.own[ri] = t2[m0 + ri]; });
-        });
-    });
-    add_to_q<B>(L, Q, acc, E);
+    const int64_t lb = logical_block();
+#include "step_correct_body.inc"
+}
+
+// Batched forms: every workgroup finds its item in block_item[] (items of one
+// degree and precision, any number of meshes, one launch).
+template <int N, bool MIX, typename real>
+__global__ void __launch_bounds__(64) k_batch_predict(const StepItem<real> *__restrict__ items,
+                                                      const int32_t *__restrict__ block_item)
+{
+    const int64_t b = logical_block();
+    const StepItem<real> &it = items[block_item[b]];
+    const int64_t E = it.E, lb = b - it.first_block;
+    const double dt = it.dt;
+    const real *Q = it.Q, *star = it.star;
+    real *Iout = it.I, *traces = it.traces;
+#include "step_predict_body.inc"
+}
+
+template <int N, bool MIX, typename real>
+__global__ void __launch_bounds__(64) k_batch_correct(const StepItem<real> *__restrict__ items,
+                                                      const int32_t *__restrict__ block_item)
+{
+    const int64_t b = logical_block();
+    const StepItem<real> &it = items[block_item[b]];
+    const int64_t E = it.E, lb = b - it.first_block;
+    const real *Iin = it.I, *traces = it.traces, *star = it.star;
+    const double *Ap = it.Ap, *Am = it.Am;
+    const int32_t *neigh = it.neigh;
+    const uint8_t *face_rot = it.face_rot;
+    real *Q = it.Q;
+#include "step_correct_body.inc"
 }
 
 // dense star [E][3][9][9] (FP64) -> packed [E][9][3][3] (real)

@@ -1,5 +1,8 @@
 // Launchers of the element kernels for one polynomial degree (DG_DEGREE),
 // both precisions.  Compiled once per supported degree.
+#include <cstring>
+#include <type_traits>
+
 #include "dg_kernels.hip"
 #include "dg_internal.h"
 
@@ -21,8 +24,10 @@ inline unsigned flat_blocks(int64_t n)
     return (unsigned)b;
 }
 
-template <typename real>
+template <typename real, bool MIX>
 struct Launch {
+    static_assert(sizeof(dgk::StepItem<real>) == sizeof(DgItem), "StepItem layout");
+
     static hipError_t pack_star(int64_t E, const double *dense, void *packed, hipStream_t s)
     {
         if (E == 0) return hipSuccess;
@@ -64,7 +69,7 @@ struct Launch {
     static hipError_t local_flux(int64_t E, const void *I, const double *Ap, void *Q, hipStream_t s)
     {
         if (E == 0) return hipSuccess;
-        hipLaunchKernelGGL((dgk::k_local_flux<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E,
+        hipLaunchKernelGGL((dgk::k_local_flux<N, MIX, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E,
                            (const real *)I, Ap, (real *)Q);
         return hipGetLastError();
     }
@@ -72,26 +77,37 @@ struct Launch {
                                      const uint8_t *fr, const double *Am, void *Q, hipStream_t s)
     {
         if (E == 0) return hipSuccess;
-        hipLaunchKernelGGL((dgk::k_neighbour_flux<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, nI,
+        hipLaunchKernelGGL((dgk::k_neighbour_flux<N, MIX, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, nI,
                            (const real *)I, neigh, fr, Am, (real *)Q);
         return hipGetLastError();
     }
-    static hipError_t step_predict(int64_t E, double dt, const void *Q, const void *star, void *I, void *traces,
-                                   hipStream_t s)
+    static hipError_t step_predict(const DgItem &it, hipStream_t s)
     {
-        if (E == 0) return hipSuccess;
-        hipLaunchKernelGGL((dgk::k_step_predict<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (real)dt,
-                           (const real *)Q, (const real *)star, (real *)I, (real *)traces);
+        if (it.E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_step_predict<N, MIX, real>), dim3(wave_blocks(it.E)), dim3(64), 0, s, it.E, it.dt,
+                           (const real *)it.Q, (const real *)it.star, (real *)it.I, (real *)it.traces);
         return hipGetLastError();
     }
-    static hipError_t step_correct(int64_t E, const void *I, const void *traces, const void *star,
-                                   const double *Ap, const double *Am, const int32_t *neigh, const uint8_t *fr,
-                                   void *Q, hipStream_t s)
+    static hipError_t step_correct(const DgItem &it, hipStream_t s)
     {
-        if (E == 0) return hipSuccess;
-        hipLaunchKernelGGL((dgk::k_step_correct<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E,
-                           (const real *)I, (const real *)traces, (const real *)star, Ap, Am, neigh, fr,
-                           (real *)Q);
+        if (it.E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_step_correct<N, MIX, real>), dim3(wave_blocks(it.E)), dim3(64), 0, s, it.E,
+                           (const real *)it.I, (const real *)it.traces, (const real *)it.star, it.Ap, it.Am,
+                           it.neigh, it.face_rot, (real *)it.Q);
+        return hipGetLastError();
+    }
+    static hipError_t batch_predict(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s)
+    {
+        if (nblocks == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_batch_predict<N, MIX, real>), dim3((unsigned)nblocks), dim3(64), 0, s,
+                           (const dgk::StepItem<real> *)items, block_item);
+        return hipGetLastError();
+    }
+    static hipError_t batch_correct(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s)
+    {
+        if (nblocks == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_batch_correct<N, MIX, real>), dim3((unsigned)nblocks), dim3(64), 0, s,
+                           (const dgk::StepItem<real> *)items, block_item);
         return hipGetLastError();
     }
     static void fill(DgTable *t)
@@ -104,6 +120,8 @@ struct Launch {
         t->neighbour_flux = neighbour_flux;
         t->step_predict = step_predict;
         t->step_correct = step_correct;
+        t->batch_predict = batch_predict;
+        t->batch_correct = batch_correct;
     }
 };
 
@@ -112,8 +130,17 @@ struct Launch {
 #define DG_CAT2(a, b) a##b
 #define DG_CAT(a, b) DG_CAT2(a, b)
 
-void DG_CAT(dg_table_, DG_DEGREE)(DgTable *fp64, DgTable *fp32)
+void DG_CAT(dg_table_, DG_DEGREE)(DgTable *fp64, DgTable *fp32, DgTable *mixed)
 {
-    Launch<double>::fill(fp64);
-    Launch<float>::fill(fp32);
+    Launch<double, false>::fill(fp64);
+    Launch<float, false>::fill(fp32);
+    // mixed form: FP32 storage and contractions; it differs from plain FP32
+    // in the time-integral accumulation and the flux-solver products (FP64)
+    Launch<float, false>::fill(mixed);
+    mixed->local_flux = Launch<float, true>::local_flux;
+    mixed->neighbour_flux = Launch<float, true>::neighbour_flux;
+    mixed->step_predict = Launch<float, true>::step_predict;
+    mixed->step_correct = Launch<float, true>::step_correct;
+    mixed->batch_predict = Launch<float, true>::batch_predict;
+    mixed->batch_correct = Launch<float, true>::batch_correct;
 }

@@ -13,7 +13,7 @@ from oracle import refmat, stages
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 1: 1e-5}
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-5}
 
 
 def _dev(a, dtype=None):
@@ -38,7 +38,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("N,E", [(2, 30), (3, 52), (4, 17), (5, 52), (6, 23)])
 def test_stages(N, E, prec):
     _say(f"test_stages N={N} E={E} prec={prec}")
@@ -77,7 +77,7 @@ def test_stages(N, E, prec):
     assert dgtest.rel_err(inc, stages.volume(rm, d["star"], d["I"])) <= tol * 10
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_step_config0(prec):
     """One full time step on the 8x8x8x6 = 3072-element jittered periodic mesh,
     degree 3, random materials; element data built by the library itself."""
@@ -197,3 +197,67 @@ def test_full_size_config1_sampled():
     ref = stages.step_subset(refmat.refmats(N), dt, ids, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface,
                              mesh.orient)
     assert dgtest.rel_err(Q1[ids] - Q[ids], ref - Q[ids]) <= 1e-12
+
+
+def _mesh_tensors(dg, N, n, seed_index, prec, relabel=True):
+    mesh, mats, Q, dt = dgtest.mesh_inputs(n, N, seed_index, relabel=relabel)
+    plan = dg.Plan(N, prec)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    m = dict(degree=N, E=E, dt=dt, Q=_dev(Q, plan.dtype),
+             I=torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0"),
+             traces=torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0"),
+             star_packed=plan.pack_star(_dev(star)), Aplus=_dev(Ap), Aminus=_dev(Am),
+             neigh=_dev(mesh.neigh), face_rot=_dev(mesh.face_rot))
+    return plan, m, (mesh, mats, Q, dt)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batch_mixed_degrees(prec):
+    """Five meshes of degrees 2..6 stepped as one batch (graph replay): each
+    mesh equals its own single-mesh dg_step bitwise, and the FP64 oracle."""
+    import paper_1903_11521_amd as dg
+    _say(f"test_batch_mixed_degrees prec={prec}")
+    meshes, singles, raw = [], [], []
+    for i, (N, n) in enumerate([(2, 4), (5, 3), (3, 3), (6, 3), (4, 4)]):
+        plan, m, r = _mesh_tensors(dg, N, n, 10 + i, prec)
+        meshes.append(m)
+        raw.append(r)
+        q = m["Q"].clone()
+        plan.step(q, torch.empty_like(m["I"]), torch.empty_like(m["traces"]), m["star_packed"], m["Aplus"],
+                  m["Aminus"], m["neigh"], m["face_rot"], m["dt"], 3)
+        singles.append(q)
+    batch = dg.Batch(prec, meshes)
+    batch.step(2)
+    batch.step(1)
+    torch.cuda.synchronize()
+    for m, q, (mesh, mats, Q, dt) in zip(meshes, singles, raw):
+        assert torch.equal(m["Q"], q), "batch differs from single-mesh step (degree %d)" % m["degree"]
+        N = m["degree"]
+        ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+        ref = Q.copy()
+        for _ in range(3):
+            ref = stages.step(refmat.refmats(N), dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+        Qin = Q.astype(np.float32).astype(np.float64) if prec else Q
+        assert dgtest.rel_err(_host(m["Q"]) - Qin, ref - Q) <= TOL[prec] * (30 if prec else 1)
+    batch.close()
+
+
+def test_mixed_is_at_least_as_accurate_as_fp32():
+    """The mixed form (FP64 time integral and flux products) is not less
+    accurate than plain FP32 against the FP64 oracle (degree 5, 3 steps)."""
+    import paper_1903_11521_amd as dg
+    N = 5
+    errs = {}
+    for prec in (1, 2):
+        plan, m, (mesh, mats, Q, dt) = _mesh_tensors(dg, N, 3, 30, prec)
+        plan.step(m["Q"], m["I"], m["traces"], m["star_packed"], m["Aplus"], m["Aminus"], m["neigh"],
+                  m["face_rot"], dt, 3)
+        ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+        ref = Q.copy()
+        for _ in range(3):
+            ref = stages.step(refmat.refmats(N), dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+        errs[prec] = dgtest.rel_err(_host(m["Q"]) - Q.astype(np.float32).astype(np.float64), ref - Q)
+    _say("fp32 %.3e mixed %.3e" % (errs[1], errs[2]))
+    assert errs[2] <= 1e-5 and errs[1] <= 1e-5
+    assert errs[2] <= errs[1] * 1.5
