@@ -40,9 +40,14 @@ def parse():
     ap.add_argument("--n", type=int, default=40, help="cubes per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched"], default="single",
-                    help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree")
+    ap.add_argument("--workload", choices=["single", "batched", "serving"], default="single",
+                    help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
+                         "serving: Poisson arrivals of ensemble requests")
     ap.add_argument("--meshes", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -52,8 +57,9 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dg_kernels.hip", "dg_launch.hip", "refmat.cpp"):
-        with open(os.path.join(ROOT, "paper_1903_11521_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/dg_kernels.hip", "csrc/dg_launch.hip", "csrc/step_predict_body.inc",
+              "csrc/step_correct_body.inc", "csrc/refmat.cpp", "codegen.py"):
+        with open(os.path.join(ROOT, "paper_1903_11521_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -166,14 +172,81 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def serving(args):
+    """Poisson arrivals of independent simulations: E ~ log-uniform[5k, 500k]
+    elements (cube-split meshes), degree U{3..6}, U{50..500} steps, random
+    materials; admitted by HBM footprint (80 % of free HBM), DOFs resident,
+    steps of all admitted requests batched per launch (mixed precision by
+    default)."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd.serving import GpuExecutor, Request, Server
+    from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
+    from math import comb
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
+    rng = np.random.Generator(np.random.PCG64(seed_for(4)))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.requests))
+    arrivals -= arrivals[0]
+    sizes = np.exp(rng.uniform(np.log(5e3), np.log(500e3), args.requests))
+    degrees = rng.integers(3, 7, args.requests)
+    steps = rng.integers(50, 501, args.requests)
+
+    def make(i):
+        n = max(3, int(round((sizes[i] / 6) ** (1 / 3))))
+        N = int(degrees[i])
+        seed = seed_for(4) + 1000 * (i + 1)
+
+        def build():
+            mesh = cube_mesh(n, seed)
+            mats = random_materials(mesh.E, seed)
+            star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+            return dict(dt=dt_from_mesh(mesh, mats), Q=random_dofs(mesh.E, 9, comb(N + 3, 3), seed), star=star,
+                        Aplus=Ap, Aminus=Am, neigh=mesh.neigh, face_rot=mesh.face_rot)
+        return Request(rid=i, degree=N, E=6 * n ** 3, n_steps=int(steps[i]), arrival=float(arrivals[i]),
+                       build=build)
+
+    free, _ = torch.cuda.mem_get_info()
+    itemsize = 8 if prec == dg.DG_FP64 else 4
+    srv = Server(GpuExecutor(prec), int(0.8 * free), itemsize)
+    for i in range(args.requests):
+        srv.submit(make(i))
+    log("serving %d requests at %.1f req/s" % (args.requests, args.rate))
+    srv.run()
+    s = srv.summary()
+    out = {"metric": "element-updates/s", "value": s["element_updates_per_s"], "unit": "element-updates/s",
+           "n_gpus": 1, "steps": int(steps.sum()), "warmup": 0,
+           "ms_per_step": s["p50_step_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
+           "data": "synthetic",
+           "config": {"workload": "serving: %d Poisson arrivals at %.1f req/s, cube-split meshes 5k-500k elements "
+                                  "(log-uniform), degree 3..6, 50-500 steps each, continuous batching"
+                                  % (args.requests, args.rate), "rate": args.rate},
+           "serving": s}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
                           "note (DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")      # 1 GiB
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel() * 8}), flush=True)
+        return
     if args.workload == "batched":
         return batched(args)
+    if args.workload == "serving":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"
+        return serving(args)
     import torch
 
     import paper_1903_11521_amd as dg
