@@ -73,6 +73,22 @@ class Emitter:
         self.lines.append(s)
 
 
+# A scheduling fence after every FENCE FMAs of a functor.  Each FP64 literal is
+# materialised by two scalar moves; without fences the scheduler hoists the
+# moves of a whole row block, overflows the SGPRs and spills them into VGPR
+# lanes (readlane/writelane), which costs more VGPRs than the accumulators.
+FENCE = 16
+
+
+def fenced(stms):
+    out = []
+    for i, s in enumerate(stms):
+        out.append(s)
+        if (i + 1) % FENCE == 0 and i + 1 < len(stms):
+            out.append("__builtin_amdgcn_sched_barrier(0);")
+    return out
+
+
 def _degrees(N):
     return [i + j + k for dd in range(N + 1) for k in range(dd + 1) for j in range(dd - k + 1)
             for i in (dd - j - k,)]
@@ -80,8 +96,13 @@ def _degrees(N):
 
 def check_structure(N, M):
     """Properties the kernels rely on: Kt^d[k][l] != 0 only for deg(k) <
-    deg(l) (derivative staircase) and Kh non-zero only in the first
-    C(N+2,3) columns."""
+    deg(l) (derivative staircase), Kh non-zero only in the first
+    C(N+2,3) columns, f^h block diagonal by face-basis degree."""
+    fdeg = np.array([dd for dd in range(N + 1) for _ in range(dd + 1)])
+    for h in range(3):
+        m, n = np.nonzero(M["f"][h])
+        if not np.all(fdeg[m] == fdeg[n]):
+            raise RuntimeError("f is not block diagonal by degree")
     deg = np.array(_degrees(N))
     for d in range(3):
         k, l = np.nonzero(M["Kt"][d])
@@ -118,7 +139,7 @@ def gen_degree(em, N, M):
         add(cname, vals)
         for L in range(B):
             em(f"template <> struct {nm}<{N}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real x0, real x1, real x2, real* __restrict__ acc) {{")
-            for s in bodies[L]:
+            for s in fenced(bodies[L]):
                 em("  " + s)
             em("} };")
     # R: trace, row(L)-major per face S, then m
@@ -132,7 +153,7 @@ def gen_degree(em, N, M):
                     stm.append(f"tr[{m}] = fma({_lit(v)}, v, tr[{m}]);")
                     vals.append(v)
             em(f"template <> struct RCol<{N}, {S}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real v, real* __restrict__ tr) {{")
-            for s in stm:
+            for s in fenced(stm):
                 em("  " + s)
             em("} };")
         add(f"g_R{N}_{S}", vals)
@@ -147,7 +168,7 @@ def gen_degree(em, N, M):
                     stm.append(f"acc[{k}] = fma({_lit(v)}, g, acc[{k}]);")
                     vals.append(v)
             em(f"template <> struct RhCol<{N}, {S}, {Mi}> {{ template <typename real> __device__ __forceinline__ static void apply(real g, real* __restrict__ acc) {{")
-            for s in stm:
+            for s in fenced(stm):
                 em("  " + s)
             em("} };")
         add(f"g_Rh{N}_{S}", vals)
@@ -168,6 +189,23 @@ def gen_degree(em, N, M):
                 vals.append(v)
         em("} };")
         add(f"g_F{N}_{H}", vals)
+    # f^h one degree block at a time (f^h is block diagonal by degree: the
+    # orientation maps are measure-preserving affine symmetries of the
+    # reference triangle, which keep each degree's orthogonal subspace)
+    for H in range(3):
+        for d in range(N + 1):
+            off = d * (d + 1) // 2
+            em(f"template <> struct FBlock<{N}, {H}, {d}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ in, real* __restrict__ out) {{")
+            for i in range(d + 1):
+                terms = [(j, M["f"][H, off + i, off + j]) for j in range(d + 1) if M["f"][H, off + i, off + j] != 0.0]
+                if not terms:
+                    em(f"  out[{i}] = real(0);")
+                    continue
+                j0, v0 = terms[0]
+                em(f"  out[{i}] = {_lit(v0)} * in[{j0}];")
+                for j, v in terms[1:]:
+                    em(f"  out[{i}] = fma({_lit(v)}, in[{j}], out[{i}]);")
+            em("} };")
     return consts
 
 
@@ -193,6 +231,7 @@ def generate(host_lib_path, out_path):
     em("template <int N, int S, int L> struct RCol;")
     em("template <int N, int S, int M> struct RhCol;")
     em("template <int N, int H> struct FApply;")
+    em("template <int N, int H, int D> struct FBlock;")
     allc = {}
     stats = {}
     for N in DEGREES:
@@ -201,8 +240,8 @@ def generate(host_lib_path, out_path):
         stats[N] = flop_counts(M, N)
     body = em.lines
     em2 = Emitter()
-    em2.lines = body[:7]
-    em2.lines += body[7:]
+    em2.lines = body[:8]
+    em2.lines += body[8:]
     with open(out_path + ".tmp", "w") as fh:
         fh.write("\n".join(em2.lines) + "\n")
     os.replace(out_path + ".tmp", out_path)

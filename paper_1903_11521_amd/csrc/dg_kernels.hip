@@ -11,7 +11,7 @@
 // each matrix, so structural zeros cost nothing and the matrices need no
 // memory traffic).  Contractions over the
 // quantity index (star matrices, flux solvers) mix columns; those go through
-// a 16-row LDS chunk buffer.  All global traffic of element-major arrays is
+// an LDS chunk buffer (32 or 64 rows per column).  All global traffic of element-major arrays is
 // staged through the same buffer so that it is fully coalesced.
 //
 // Arrays are element major: Q, I [E][9][B]; T [E][N+1][9][B] (Taylor-scaled
@@ -29,8 +29,15 @@ namespace dgk {
 
 constexpr int EPW = 7;     // elements per wavefront
 constexpr int NQ = 9;      // elastic quantities
-constexpr int CH = 16;     // rows per LDS chunk
-constexpr int LB = CH + 1; // padded row stride of a column in LDS
+#ifndef DG_DEGREE
+#error "DG_DEGREE (the polynomial degree of this translation unit) must be defined"
+#endif
+// Rows per LDS chunk (LDS budget: 19 KB per one-wave workgroup in FP64,
+// 9.5 KB in FP32); 32 rows hold every face-basis column (Bf <= 28).
+template <typename real>
+constexpr int CH = 32;
+template <typename real>
+constexpr int LB = CH<real> + 1;   // padded (odd) row stride of a column in LDS
 constexpr int NCOL = 8 * NQ;
 
 __host__ __device__ constexpr int nb3(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
@@ -65,7 +72,7 @@ struct Lane {
     int lane, e, p;
     int64_t base, elem;
     bool active;
-    real *buf;      // LDS chunk buffer [8][9][LB]
+    real *buf;      // LDS chunk buffer [8][9][LB<real>]
     real *own;      // this lane's column in buf
 };
 
@@ -91,11 +98,21 @@ __device__ __forceinline__ Lane<real> make_lane(real *buf, int64_t E, int64_t lb
     L.active = (L.e < EPW) && (el < E);
     L.elem = el < E ? el : E - 1;
     L.buf = buf;
-    L.own = buf + (L.e * NQ + L.p) * LB;
+    L.own = buf + (L.e * NQ + L.p) * LB<real>;
     return L;
 }
 
 __device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+// Scheduling fence every SB rows of an unrolled contraction: keeps the
+// scheduler from hoisting a whole chunk's LDS reads above its FMAs, which
+// would cost one register pair per hoisted value.
+constexpr int SB = 4;
+template <int R>
+__device__ __forceinline__ void row_fence()
+{
+    if constexpr (R % SB == SB - 1) __builtin_amdgcn_sched_barrier(0);
+}
 
 // element of column slot c (0..71) of this wave, clamped into range
 __device__ __forceinline__ int64_t slot_elem(int64_t base, int c, int64_t E)
@@ -105,14 +122,37 @@ __device__ __forceinline__ int64_t slot_elem(int64_t base, int c, int64_t E)
 }
 
 // Cooperative, coalesced load of rows [l0, l0+cnt) of every column slot into
-// LDS.  colptr(c) returns the global address of row 0 of column slot c.
+// LDS.  colptr(c) returns the global address of row 0 of column slot c (or
+// null: zeros).  Loads are issued in groups of LDG before their LDS writes,
+// so a chunk costs about IT/LDG memory latencies instead of IT (a fully
+// unrolled chunk costs too many registers next to the accumulators).
+constexpr int LDG = 6;
+
 template <int CNT, typename real, typename SrcT, typename ColPtr>
 __device__ __forceinline__ void chunk_load(const Lane<real> &L, ColPtr colptr, int l0)
 {
-    for (int idx = L.lane; idx < NCOL * CNT; idx += 64) {
-        const int c = idx / CNT, r = idx - c * CNT;
-        const SrcT *src = colptr(c);
-        L.buf[c * LB + r] = src ? (real)src[l0 + r] : real(0);
+    constexpr int TOT = NCOL * CNT, IT = (TOT + 63) / 64, NG = (IT + LDG - 1) / LDG;
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        real v[LDG];
+#pragma unroll
+        for (int u = 0; u < LDG; ++u) {
+            const int idx = L.lane + 64 * (g * LDG + u);
+            v[u] = real(0);
+            if (idx < TOT) {
+                const int c = idx / CNT, r = idx - c * CNT;
+                const SrcT *src = colptr(c);
+                if (src) v[u] = (real)src[l0 + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LDG; ++u) {
+            const int idx = L.lane + 64 * (g * LDG + u);
+            if (idx < TOT) {
+                const int c = idx / CNT, r = idx - c * CNT;
+                L.buf[c * LB<real> + r] = v[u];
+            }
+        }
     }
 }
 
@@ -121,9 +161,14 @@ __device__ __forceinline__ void chunk_load(const Lane<real> &L, ColPtr colptr, i
 template <int CNT, typename real, typename ColPtr>
 __device__ __forceinline__ void chunk_store(const Lane<real> &L, ColPtr colptr, int l0, int64_t E)
 {
-    for (int idx = L.lane; idx < EPW * NQ * CNT; idx += 64) {
-        const int c = idx / CNT, r = idx - c * CNT;
-        if (L.base + c / NQ < E) colptr(c)[l0 + r] = L.buf[c * LB + r];
+    constexpr int TOT = EPW * NQ * CNT, IT = (TOT + 63) / 64;
+#pragma unroll 4
+    for (int i = 0; i < IT; ++i) {
+        const int idx = L.lane + 64 * i;
+        if (idx < TOT) {
+            const int c = idx / CNT, r = idx - c * CNT;
+            if (L.base + c / NQ < E) colptr(c)[l0 + r] = L.buf[c * LB<real> + r];
+        }
     }
 }
 
@@ -131,9 +176,9 @@ __device__ __forceinline__ void chunk_store(const Lane<real> &L, ColPtr colptr, 
 template <int R, typename real, typename SrcT, typename ColPtr>
 __device__ __forceinline__ void load_columns(const Lane<real> &L, ColPtr colptr, real *dst)
 {
-    static_for<0, (R + CH - 1) / CH>([&](auto ci) {
-        constexpr int l0 = decltype(ci)::value * CH;
-        constexpr int cnt = (R - l0) < CH ? (R - l0) : CH;
+    static_for<0, (R + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (R - l0) < CH<real> ? (R - l0) : CH<real>;
         chunk_load<cnt, real, SrcT>(L, colptr, l0);
         lds_sync();
         static_for<0, cnt>([&](auto ri) { dst[l0 + ri] = L.own[ri]; });
@@ -145,9 +190,9 @@ __device__ __forceinline__ void load_columns(const Lane<real> &L, ColPtr colptr,
 template <int R, int RV, typename real, typename ColPtr>
 __device__ __forceinline__ void store_columns(const Lane<real> &L, ColPtr colptr, const real *src, int64_t E)
 {
-    static_for<0, (R + CH - 1) / CH>([&](auto ci) {
-        constexpr int l0 = decltype(ci)::value * CH;
-        constexpr int cnt = (R - l0) < CH ? (R - l0) : CH;
+    static_for<0, (R + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (R - l0) < CH<real> ? (R - l0) : CH<real>;
         static_for<0, cnt>([&](auto ri) {
             constexpr int l = l0 + decltype(ri)::value;
             if constexpr (l < RV) L.own[ri] = src[l];
@@ -164,9 +209,9 @@ template <int B, typename real>
 __device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const real *acc, int64_t E)
 {
     auto col = [&](int c) { return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
-    static_for<0, (B + CH - 1) / CH>([&](auto ci) {
-        constexpr int l0 = decltype(ci)::value * CH;
-        constexpr int cnt = (B - l0) < CH ? (B - l0) : CH;
+    static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
         chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return col(c); }, l0);
         lds_sync();
         static_for<0, cnt>([&](auto ri) { L.own[ri] += acc[l0 + ri]; });
@@ -201,14 +246,14 @@ __device__ __forceinline__ Star<real> load_star(const Lane<real> &L, const real 
 template <int N, bool KTILDE, int NROWS, typename real, typename Fill>
 __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<real> &S, real *acc, Fill fill)
 {
-    static_for<0, (NROWS + CH - 1) / CH>([&](auto ci) {
-        constexpr int l0 = decltype(ci)::value * CH;
-        constexpr int cnt = (NROWS - l0) < CH ? (NROWS - l0) : CH;
+    static_for<0, (NROWS + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (NROWS - l0) < CH<real> ? (NROWS - l0) : CH<real>;
         fill(std::integral_constant<int, l0>{}, std::integral_constant<int, cnt>{});
         lds_sync();
-        const real *b0 = L.buf + (L.e * NQ + S.q0) * LB;
-        const real *b1 = L.buf + (L.e * NQ + S.q1) * LB;
-        const real *b2 = L.buf + (L.e * NQ + S.q2) * LB;
+        const real *b0 = L.buf + (L.e * NQ + S.q0) * LB<real>;
+        const real *b1 = L.buf + (L.e * NQ + S.q1) * LB<real>;
+        const real *b2 = L.buf + (L.e * NQ + S.q2) * LB<real>;
         static_for<0, cnt>([&](auto ri) {
             constexpr int l = l0 + decltype(ri)::value;
             const real v0 = b0[ri], v1 = b1[ri], v2 = b2[ri];
@@ -217,6 +262,7 @@ __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<re
             const real x2 = fma(S.s[2][0], v0, fma(S.s[2][1], v1, S.s[2][2] * v2));
             if constexpr (KTILDE) KtCol<N, l>::apply(x0, x1, x2, acc);
             else KhCol<N, l>::apply(x0, x1, x2, acc);
+            row_fence<decltype(ri)::value>();
         });
         lds_sync();
     });
@@ -234,20 +280,51 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
     mreal a[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) a[q] = (mreal)A[L.p * NQ + q];
-    const real *xe = L.buf + L.e * NQ * LB;
-    static_for<0, (Bf + CH - 1) / CH>([&](auto ci) {
-        constexpr int m0 = decltype(ci)::value * CH;
-        constexpr int cnt = (Bf - m0) < CH ? (Bf - m0) : CH;
+    const real *xe = L.buf + L.e * NQ * LB<real>;
+    static_for<0, (Bf + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int m0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (Bf - m0) < CH<real> ? (Bf - m0) : CH<real>;
         fill(std::integral_constant<int, m0>{}, std::integral_constant<int, cnt>{});
         lds_sync();
         static_for<0, cnt>([&](auto ri) {
             constexpr int m = m0 + decltype(ri)::value;
             mreal g = a[0] * (mreal)xe[ri];
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) g = fma(a[q], (mreal)xe[q * LB + ri], g);
+            for (int q = 1; q < NQ; ++q) g = fma(a[q], (mreal)xe[q * LB<real> + ri], g);
             RhCol<N, S, m>::apply((real)g, acc);
+            row_fence<decltype(ri)::value>();
         });
         lds_sync();
+    });
+}
+
+// acc[k] += sum_m Rh^S[k][m] sum_n f^h[m][n] sum_q A[p][q] X[n][q] with all
+// Bf rows of X already in LDS; f^h (block diagonal by degree, runtime h) is
+// applied per degree block after the quantity product.
+template <int N, int S, bool MIX = false, typename real>
+__device__ __forceinline__ void flux_lift_oriented(const Lane<real> &L, const double *A, int h, real *acc)
+{
+    using mreal = typename std::conditional<MIX, double, real>::type;
+    static_assert(nb2(N) <= CH<real>, "face rows must fit one chunk");
+    mreal a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = (mreal)A[L.p * NQ + q];
+    const real *xe = L.buf + L.e * NQ * LB<real>;
+    static_for<0, N + 1>([&](auto di) {
+        constexpr int d = decltype(di)::value, off = d * (d + 1) / 2;
+        real g0[d + 1], g[d + 1];
+#pragma unroll
+        for (int i = 0; i < d + 1; ++i) {
+            mreal v = a[0] * (mreal)xe[off + i];
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) v = fma(a[q], (mreal)xe[q * LB<real> + off + i], v);
+            g0[i] = (real)v;
+        }
+        if (h == 0) FBlock<N, 0, d>::apply(g0, g);
+        else if (h == 1) FBlock<N, 1, d>::apply(g0, g);
+        else FBlock<N, 2, d>::apply(g0, g);
+        static_for<0, d + 1>([&](auto ii) { RhCol<N, S, off + decltype(ii)::value>::apply(g[decltype(ii)::value], acc); });
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -327,7 +404,7 @@ __global__ void __launch_bounds__(64) k_derivative(int64_t E, real dt, const rea
                                                    const real *__restrict__ star, real *__restrict__ T)
 {
     constexpr int B = nb3(N), bin = nb3(N - D), bout = nb3(N - D - 1);
-    __shared__ real buf[NCOL * LB];
+    __shared__ real buf[NCOL * LB<real>];
     const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
     auto tcol = [&](int c, int d) { return T + ((slot_elem(L.base, c, E) * (N + 1) + d) * NQ + c % NQ) * B; };
@@ -384,7 +461,7 @@ __global__ void __launch_bounds__(64) k_volume(int64_t E, const real *__restrict
                                                real *__restrict__ Q)
 {
     constexpr int B = nb3(N);
-    __shared__ real buf[NCOL * LB];
+    __shared__ real buf[NCOL * LB<real>];
     const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
     real acc[B];
@@ -401,7 +478,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
                                                    real *__restrict__ Q)
 {
     constexpr int B = nb3(N), Bf = nb2(N);
-    __shared__ real buf[NCOL * LB];
+    __shared__ real buf[NCOL * LB<real>];
     const Lane<real> L = make_lane(buf, E, logical_block());
     real acc[B], tr[Bf];
 #pragma unroll
@@ -411,9 +488,9 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
         constexpr int S = decltype(si)::value;
 #pragma unroll
         for (int m = 0; m < Bf; ++m) tr[m] = real(0);
-        static_for<0, (B + CH - 1) / CH>([&](auto ci) {
-            constexpr int l0 = decltype(ci)::value * CH;
-            constexpr int cnt = (B - l0) < CH ? (B - l0) : CH;
+        static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
+            constexpr int l0 = decltype(ci)::value * CH<real>;
+            constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
             chunk_load<cnt, real, real>(L, icol, l0);
             lds_sync();
             static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(L.own[ri], tr); });
@@ -435,7 +512,7 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
                                                        const double *__restrict__ Am, real *__restrict__ Q)
 {
     constexpr int B = nb3(N), Bf = nb2(N);
-    __shared__ real buf[NCOL * LB];
+    __shared__ real buf[NCOL * LB<real>];
     __shared__ int nbt[8][4];
     const Lane<real> L = make_lane(buf, E, logical_block());
     if (L.p == 0) {
@@ -512,7 +589,8 @@ k_step_correct(int64_t E, const real *__restrict__ Iin, const real *__restrict__
 // Batched forms: every workgroup finds its item in block_item[] (items of one
 // degree and precision, any number of meshes, one launch).
 template <int N, bool MIX, typename real>
-__global__ void __launch_bounds__(64) k_batch_predict(const StepItem<real> *__restrict__ items,
+__global__ void __launch_bounds__(64)
+k_batch_predict(const StepItem<real> *__restrict__ items,
                                                       const int32_t *__restrict__ block_item)
 {
     const int64_t b = logical_block();
@@ -525,7 +603,8 @@ __global__ void __launch_bounds__(64) k_batch_predict(const StepItem<real> *__re
 }
 
 template <int N, bool MIX, typename real>
-__global__ void __launch_bounds__(64) k_batch_correct(const StepItem<real> *__restrict__ items,
+__global__ void __launch_bounds__(64)
+k_batch_correct(const StepItem<real> *__restrict__ items,
                                                       const int32_t *__restrict__ block_item)
 {
     const int64_t b = logical_block();
