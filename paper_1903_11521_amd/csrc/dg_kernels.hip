@@ -114,72 +114,101 @@ __device__ __forceinline__ void row_fence()
     if constexpr (R % SB == SB - 1) __builtin_amdgcn_sched_barrier(0);
 }
 
-// element of column slot c (0..71) of this wave, clamped into range
-__device__ __forceinline__ int64_t slot_elem(int64_t base, int c, int64_t E)
+// element of slot g (0..7) of this wave, clamped into range
+__device__ __forceinline__ int64_t slot_elem(int64_t base, int g, int64_t E)
 {
-    const int64_t el = base + c / NQ;
+    const int64_t el = base + g;
     return el < E ? el : E - 1;
 }
 
-// Cooperative, coalesced load of rows [l0, l0+cnt) of every column slot into
-// LDS.  colptr(c) returns the global address of row 0 of column slot c (or
-// null: zeros).  Loads are issued in groups of LDG before their LDS writes,
-// so a chunk costs about IT/LDG memory latencies instead of IT (a fully
-// unrolled chunk costs too many registers next to the accumulators).
-constexpr int LDG = 6;
+// Rows of a missing element (no neighbour) are read from here: zero-filled
+// static storage, longer than any element block.
+__device__ double dg_zero_block[1024];
 
-template <int CNT, typename real, typename SrcT, typename ColPtr>
-__device__ __forceinline__ void chunk_load(const Lane<real> &L, ColPtr colptr, int l0)
+// Lanes move element data in groups of 8: lane (g, s) = (lane / 8, lane % 8)
+// handles rows s, s+8, ... of the 9 columns of element slot g, so every
+// global and LDS address is the lane's base plus a compile-time offset (no
+// per-value index arithmetic); the 8 lanes of a group touch 8 consecutive
+// values of one column.
+template <int CNT>
+struct RowSplit {
+    static constexpr int K = (CNT + 7) / 8;          // rows per lane and column
+    static constexpr int TAIL = CNT - 8 * (K - 1);   // lanes s < TAIL own row 8(K-1)+s
+    static constexpr int GQ = (8 + K - 1) / K;       // columns per load group (about 8 loads in flight)
+};
+
+// Cooperative load of rows [l0, l0+CNT) of the 9 columns of every element
+// slot into LDS (slot g, column q, row r at buf[(g*NQ + q)*LB + r]).
+// eptr(g) is the global address of row 0 of column 0 of slot g's element
+// block, whose columns are QS apart, or null for zeros.  Branch free: in the
+// last row of a column, lanes past the chunk re-read its row 0 and write
+// rows [CNT, 8K) of their LDS column, which nothing reads (8K <= LB).
+template <int CNT, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void chunk_load(const Lane<real> &L, EPtr eptr, int l0)
 {
-    constexpr int TOT = NCOL * CNT, IT = (TOT + 63) / 64, NG = (IT + LDG - 1) / LDG;
-#pragma unroll 1
-    for (int g = 0; g < NG; ++g) {
-        real v[LDG];
-#pragma unroll
-        for (int u = 0; u < LDG; ++u) {
-            const int idx = L.lane + 64 * (g * LDG + u);
-            v[u] = real(0);
-            if (idx < TOT) {
-                const int c = idx / CNT, r = idx - c * CNT;
-                const SrcT *src = colptr(c);
-                if (src) v[u] = (real)src[l0 + r];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < LDG; ++u) {
-            const int idx = L.lane + 64 * (g * LDG + u);
-            if (idx < TOT) {
-                const int c = idx / CNT, r = idx - c * CNT;
-                L.buf[c * LB<real> + r] = v[u];
-            }
-        }
-    }
+    using RS = RowSplit<CNT>;
+    constexpr int K = RS::K, GQ = RS::GQ;
+    static_assert(8 * K <= LB<real>, "tail rows must stay inside the column slot");
+    static_assert(9 * QS <= 1024, "element block longer than the zero block");
+    const int g = L.lane >> 3, s = L.lane & 7;
+    const real *e0 = eptr(g);
+    const real *src = (e0 ? e0 : reinterpret_cast<const real *>(dg_zero_block)) + l0 + s;
+    const real *srct = s < RS::TAIL ? src + 8 * (K - 1) : src - s;   // last row, else row 0
+    real *dst = L.buf + g * NQ * LB<real> + s;
+    static_for<0, (NQ + GQ - 1) / GQ>([&](auto gi) {
+        constexpr int q0 = decltype(gi)::value * GQ, nq = (NQ - q0) < GQ ? (NQ - q0) : GQ;
+        real v[nq][K];
+        static_for<0, nq>([&](auto ji) {
+            static_for<0, K>([&](auto ki) {
+                constexpr int j = decltype(ji)::value, kk = decltype(ki)::value;
+                v[j][kk] = kk < K - 1 ? src[(q0 + j) * QS + 8 * kk] : srct[(q0 + j) * QS];
+            });
+        });
+        static_for<0, nq>([&](auto ji) {
+            static_for<0, K>([&](auto ki) {
+                constexpr int j = decltype(ji)::value, kk = decltype(ki)::value;
+                dst[(q0 + j) * LB<real> + 8 * kk] = v[j][kk];
+            });
+        });
+        __builtin_amdgcn_sched_barrier(0);   // one group of loads in flight at a time
+    });
 }
 
-// Cooperative, coalesced store of rows [l0, l0+cnt) of the real (non-shadow,
-// in-range) column slots from LDS.
-template <int CNT, typename real, typename ColPtr>
-__device__ __forceinline__ void chunk_store(const Lane<real> &L, ColPtr colptr, int l0, int64_t E)
+// Cooperative store of rows [l0, l0+CNT) of the columns of the real
+// (non-shadow, in-range) element slots from LDS; eptr as for chunk_load.
+template <int CNT, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void chunk_store(const Lane<real> &L, EPtr eptr, int l0, int64_t E)
 {
-    constexpr int TOT = EPW * NQ * CNT, IT = (TOT + 63) / 64;
-#pragma unroll 4
-    for (int i = 0; i < IT; ++i) {
-        const int idx = L.lane + 64 * i;
-        if (idx < TOT) {
-            const int c = idx / CNT, r = idx - c * CNT;
-            if (L.base + c / NQ < E) colptr(c)[l0 + r] = L.buf[c * LB<real> + r];
+    using RS = RowSplit<CNT>;
+    constexpr int K = RS::K;
+    const int g = L.lane >> 3, s = L.lane & 7;
+    if (g < EPW && L.base + g < E) {
+        real *dst = eptr(g) + l0 + s;
+        const real *src = L.buf + g * NQ * LB<real> + s;
+        static_for<0, NQ>([&](auto qi) {
+            static_for<0, K - 1>([&](auto ki) {
+                constexpr int q = decltype(qi)::value, kk = decltype(ki)::value;
+                dst[q * QS + 8 * kk] = src[q * LB<real> + 8 * kk];
+            });
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        if (s < RS::TAIL) {
+            static_for<0, NQ>([&](auto qi) {
+                constexpr int q = decltype(qi)::value;
+                dst[q * QS + 8 * (K - 1)] = src[q * LB<real> + 8 * (K - 1)];
+            });
         }
     }
 }
 
 // load this lane's own column (rows [0,R)) of an element-major array into regs
-template <int R, typename real, typename SrcT, typename ColPtr>
-__device__ __forceinline__ void load_columns(const Lane<real> &L, ColPtr colptr, real *dst)
+template <int R, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void load_columns(const Lane<real> &L, EPtr eptr, real *dst)
 {
     static_for<0, (R + CH<real> - 1) / CH<real>>([&](auto ci) {
         constexpr int l0 = decltype(ci)::value * CH<real>;
         constexpr int cnt = (R - l0) < CH<real> ? (R - l0) : CH<real>;
-        chunk_load<cnt, real, SrcT>(L, colptr, l0);
+        chunk_load<cnt, QS>(L, eptr, l0);
         lds_sync();
         static_for<0, cnt>([&](auto ri) { dst[l0 + ri] = L.own[ri]; });
         lds_sync();
@@ -187,8 +216,8 @@ __device__ __forceinline__ void load_columns(const Lane<real> &L, ColPtr colptr,
 }
 
 // store this lane's own column rows [0,R) from regs (rows >= RV written as 0)
-template <int R, int RV, typename real, typename ColPtr>
-__device__ __forceinline__ void store_columns(const Lane<real> &L, ColPtr colptr, const real *src, int64_t E)
+template <int R, int RV, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void store_columns(const Lane<real> &L, EPtr eptr, const real *src, int64_t E)
 {
     static_for<0, (R + CH<real> - 1) / CH<real>>([&](auto ci) {
         constexpr int l0 = decltype(ci)::value * CH<real>;
@@ -199,7 +228,7 @@ __device__ __forceinline__ void store_columns(const Lane<real> &L, ColPtr colptr
             else L.own[ri] = real(0);
         });
         lds_sync();
-        chunk_store<cnt>(L, colptr, l0, E);
+        chunk_store<cnt, QS>(L, eptr, l0, E);
         lds_sync();
     });
 }
@@ -208,15 +237,15 @@ __device__ __forceinline__ void store_columns(const Lane<real> &L, ColPtr colptr
 template <int B, typename real>
 __device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const real *acc, int64_t E)
 {
-    auto col = [&](int c) { return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
+    auto blk = [&](int g) { return Q + slot_elem(L.base, g, E) * NQ * B; };
     static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
         constexpr int l0 = decltype(ci)::value * CH<real>;
         constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
-        chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return col(c); }, l0);
+        chunk_load<cnt, B>(L, [&](int g) -> const real * { return blk(g); }, l0);
         lds_sync();
         static_for<0, cnt>([&](auto ri) { L.own[ri] += acc[l0 + ri]; });
         lds_sync();
-        chunk_store<cnt>(L, col, l0, E);
+        chunk_store<cnt, B>(L, blk, l0, E);
         lds_sync();
     });
 }
@@ -298,33 +327,54 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
     });
 }
 
-// acc[k] += sum_m Rh^S[k][m] sum_n f^h[m][n] sum_q A[p][q] X[n][q] with all
-// Bf rows of X already in LDS; f^h (block diagonal by degree, runtime h) is
-// applied per degree block after the quantity product.
+// col[m] <- sum_n f^h[m][n] col[n] for one face-basis column in LDS (f^h is
+// block diagonal by degree, applied one block at a time).
+template <int N, typename real>
+__device__ __forceinline__ void orient_column(real *col, int h)
+{
+    static_for<0, N + 1>([&](auto di) {
+        constexpr int d = decltype(di)::value, off = d * (d + 1) / 2;
+        real in[d + 1], out[d + 1];
+#pragma unroll
+        for (int i = 0; i < d + 1; ++i) in[i] = col[off + i];
+        if (h == 0) FBlock<N, 0, d>::apply(in, out);
+        else if (h == 1) FBlock<N, 1, d>::apply(in, out);
+        else FBlock<N, 2, d>::apply(in, out);
+#pragma unroll
+        for (int i = 0; i < d + 1; ++i) col[off + i] = out[i];
+    });
+}
+
+// Both flux terms of face S with one lift:
+// acc[k] += sum_m Rh^S[k][m] sum_q (Ap[p][q] Xo[m][q] + Am[p][q] Xn[m][q]),
+// with all Bf rows of the own traces Xo and of the (already oriented)
+// neighbour traces Xn in LDS (columns of xo_buf and xn_buf, row stride LB).
+// The local and neighbour terms are lifted by the same matrix, so summing
+// before the lift halves the lift work.  MIX: the sum runs in FP64 and is
+// rounded once before the FP32 lift.
 template <int N, int S, bool MIX = false, typename real>
-__device__ __forceinline__ void flux_lift_oriented(const Lane<real> &L, const double *A, int h, real *acc)
+__device__ __forceinline__ void flux_lift_pair(const Lane<real> &L, const double *Ap, const double *Am,
+                                               const real *xo_buf, const real *xn_buf, real *acc)
 {
     using mreal = typename std::conditional<MIX, double, real>::type;
     static_assert(nb2(N) <= CH<real>, "face rows must fit one chunk");
-    mreal a[NQ];
+    mreal ap[NQ], am[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) a[q] = (mreal)A[L.p * NQ + q];
-    const real *xe = L.buf + L.e * NQ * LB<real>;
-    static_for<0, N + 1>([&](auto di) {
-        constexpr int d = decltype(di)::value, off = d * (d + 1) / 2;
-        real g0[d + 1], g[d + 1];
+    for (int q = 0; q < NQ; ++q) {
+        ap[q] = (mreal)Ap[L.p * NQ + q];
+        am[q] = (mreal)Am[L.p * NQ + q];
+    }
+    const real *xo = xo_buf + L.e * NQ * LB<real>;
+    const real *xn = xn_buf + L.e * NQ * LB<real>;
+    static_for<0, nb2(N)>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        mreal g = ap[0] * (mreal)xo[m];
 #pragma unroll
-        for (int i = 0; i < d + 1; ++i) {
-            mreal v = a[0] * (mreal)xe[off + i];
+        for (int q = 1; q < NQ; ++q) g = fma(ap[q], (mreal)xo[q * LB<real> + m], g);
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) v = fma(a[q], (mreal)xe[q * LB<real> + off + i], v);
-            g0[i] = (real)v;
-        }
-        if (h == 0) FBlock<N, 0, d>::apply(g0, g);
-        else if (h == 1) FBlock<N, 1, d>::apply(g0, g);
-        else FBlock<N, 2, d>::apply(g0, g);
-        static_for<0, d + 1>([&](auto ii) { RhCol<N, S, off + decltype(ii)::value>::apply(g[decltype(ii)::value], acc); });
-        __builtin_amdgcn_sched_barrier(0);
+        for (int q = 0; q < NQ; ++q) g = fma(am[q], (mreal)xn[q * LB<real> + m], g);
+        RhCol<N, S, m>::apply((real)g, acc);
+        row_fence<m>();
     });
 }
 
@@ -365,7 +415,7 @@ __device__ __forceinline__ void orient_rt(int h, const real *in, real *out)
 // ALIAS: src and I are the same array (T^0 = Q accumulates into I in place).
 template <int N, int D, bool WRITE_T, bool ACC_I, bool ALIAS, typename real, typename ireal, typename TColPtr>
 __device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real> &S, ireal dt, real *src,
-                                           ireal *I, TColPtr tcol, int64_t E)
+                                           ireal *I, TColPtr tblk, int64_t E)
 {
     constexpr int B = nb3(N);
     if constexpr (D < N) {
@@ -391,8 +441,8 @@ __device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real>
             acc[k] *= sc;
             if constexpr (ACC_I) I[k] = fma(si, (ireal)acc[k], I[k]);
         }
-        if constexpr (WRITE_T) store_columns<B, bout>(L, [&](int c) { return tcol(c, D + 1); }, acc, E);
-        ck_recurse<N, D + 1, WRITE_T, ACC_I, ALIAS>(L, S, dt, acc, I, tcol, E);
+        if constexpr (WRITE_T) store_columns<B, bout, B>(L, [&](int g) { return tblk(g, D + 1); }, acc, E);
+        ck_recurse<N, D + 1, WRITE_T, ACC_I, ALIAS>(L, S, dt, acc, I, tblk, E);
     }
 }
 
@@ -407,25 +457,24 @@ __global__ void __launch_bounds__(64) k_derivative(int64_t E, real dt, const rea
     __shared__ real buf[NCOL * LB<real>];
     const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
-    auto tcol = [&](int c, int d) { return T + ((slot_elem(L.base, c, E) * (N + 1) + d) * NQ + c % NQ) * B; };
+    auto tblk = [&](int g, int d) { return T + (slot_elem(L.base, g, E) * (N + 1) + d) * NQ * B; };
     real acc[bout];
 #pragma unroll
     for (int k = 0; k < bout; ++k) acc[k] = real(0);
     star_contract<N, true, bin>(L, S, acc, [&](auto l0c, auto cntc) {
         constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
         if constexpr (D == 0) {
-            chunk_load<cnt, real, real>(L, [&](int c) -> const real * {
-                return Q + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, l0);
+            chunk_load<cnt, B>(L, [&](int g) -> const real * { return Q + slot_elem(L.base, g, E) * NQ * B; }, l0);
             lds_sync();
-            chunk_store<cnt>(L, [&](int c) { return tcol(c, 0); }, l0, E);
+            chunk_store<cnt, B>(L, [&](int g) { return tblk(g, 0); }, l0, E);
         } else {
-            chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return tcol(c, D); }, l0);
+            chunk_load<cnt, B>(L, [&](int g) -> const real * { return tblk(g, D); }, l0);
         }
     });
     const real sc = dt / real(D + 1);
 #pragma unroll
     for (int k = 0; k < bout; ++k) acc[k] *= sc;
-    store_columns<B, bout>(L, [&](int c) { return tcol(c, D + 1); }, acc, E);
+    store_columns<B, bout, B>(L, [&](int g) { return tblk(g, D + 1); }, acc, E);
 }
 
 // Time integral over stored Taylor-scaled derivatives (FP64 accumulation).
@@ -452,7 +501,7 @@ __device__ __forceinline__ void volume_acc(const Lane<real> &L, const Star<real>
     constexpr int B = nb3(N), Bv = nb3(N - 1);
     star_contract<N, false, Bv>(L, S, acc, [&](auto l0c, auto cntc) {
         constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
-        chunk_load<cnt, real, real>(L, [&](int c) -> const real * { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; }, l0);
+        chunk_load<cnt, B>(L, [&](int g) -> const real * { return I + slot_elem(L.base, g, E) * NQ * B; }, l0);
     });
 }
 
@@ -483,7 +532,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
     real acc[B], tr[Bf];
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = real(0);
-    auto icol = [&](int c) -> const real * { return I + (slot_elem(L.base, c, E) * NQ + c % NQ) * B; };
+    auto iblk = [&](int g) -> const real * { return I + slot_elem(L.base, g, E) * NQ * B; };
     static_for<0, 4>([&](auto si) {
         constexpr int S = decltype(si)::value;
 #pragma unroll
@@ -491,7 +540,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
         static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
             constexpr int l0 = decltype(ci)::value * CH<real>;
             constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
-            chunk_load<cnt, real, real>(L, icol, l0);
+            chunk_load<cnt, B>(L, iblk, l0);
             lds_sync();
             static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(L.own[ri], tr); });
             lds_sync();
@@ -528,9 +577,9 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
     for (int k = 0; k < B; ++k) acc[k] = real(0);
     static_for<0, 4>([&](auto si) {
         constexpr int S = decltype(si)::value;
-        load_columns<B, real, real>(L, [&](int c) -> const real * {
-            const int nu = nbt[c / NQ][S];
-            return nu >= 0 ? I + ((int64_t)nu * NQ + c % NQ) * B : nullptr;
+        load_columns<B, B>(L, [&](int g) -> const real * {
+            const int nu = nbt[g][S];
+            return nu >= 0 ? I + (int64_t)nu * NQ * B : nullptr;
         }, In);
         const int nu = nbt[L.e][S];
         const uint8_t fr = face_rot[L.elem * 4 + S];
