@@ -114,6 +114,23 @@ __device__ __forceinline__ void row_fence()
     if constexpr (R % SB == SB - 1) __builtin_amdgcn_sched_barrier(0);
 }
 
+// Condition of a code block that always runs.  In FP64 the value is opaque
+// to the compiler, so every block is a basic block of its own and the
+// compiler materialises the literal matrix entries per block instead of
+// keeping each distinct value in a scalar register across the whole kernel
+// (which overflows the scalar file into vector-lane spills).
+template <typename real>
+__device__ __forceinline__ bool code_block()
+{
+    if constexpr (sizeof(real) == 8) {
+        int v;
+        asm volatile("s_mov_b32 %0, 1" : "=s"(v));
+        return v != 0;
+    } else {
+        return true;
+    }
+}
+
 // element of slot g (0..7) of this wave, clamped into range
 __device__ __forceinline__ int64_t slot_elem(int64_t base, int g, int64_t E)
 {
@@ -272,7 +289,7 @@ __device__ __forceinline__ Star<real> load_star(const Lane<real> &L, const real 
 // acc[k] += sum_d K^d[k][l] (sum_q star^d[p][q] X[l][q]) for rows l in
 // [0, NROWS) whose values sit in LDS chunk-wise; `fill(l0, cnt)` brings rows
 // [l0, l0+cnt) of all column slots into LDS.
-template <int N, bool KTILDE, int NROWS, typename real, typename Fill>
+template <int N, bool KTILDE, int NROWS, bool BLOCKS = true, typename real, typename Fill>
 __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<real> &S, real *acc, Fill fill)
 {
     static_for<0, (NROWS + CH<real> - 1) / CH<real>>([&](auto ci) {
@@ -283,15 +300,20 @@ __device__ __forceinline__ void star_contract(const Lane<real> &L, const Star<re
         const real *b0 = L.buf + (L.e * NQ + S.q0) * LB<real>;
         const real *b1 = L.buf + (L.e * NQ + S.q1) * LB<real>;
         const real *b2 = L.buf + (L.e * NQ + S.q2) * LB<real>;
-        static_for<0, cnt>([&](auto ri) {
-            constexpr int l = l0 + decltype(ri)::value;
-            const real v0 = b0[ri], v1 = b1[ri], v2 = b2[ri];
-            const real x0 = fma(S.s[0][0], v0, fma(S.s[0][1], v1, S.s[0][2] * v2));
-            const real x1 = fma(S.s[1][0], v0, fma(S.s[1][1], v1, S.s[1][2] * v2));
-            const real x2 = fma(S.s[2][0], v0, fma(S.s[2][1], v1, S.s[2][2] * v2));
-            if constexpr (KTILDE) KtCol<N, l>::apply(x0, x1, x2, acc);
-            else KhCol<N, l>::apply(x0, x1, x2, acc);
-            row_fence<decltype(ri)::value>();
+        static_for<0, (cnt + SB - 1) / SB>([&](auto bi) {
+            constexpr int r0 = decltype(bi)::value * SB, rn = (cnt - r0) < SB ? (cnt - r0) : SB;
+            if (!BLOCKS || code_block<real>()) {
+                static_for<0, rn>([&](auto rj) {
+                    constexpr int ri = r0 + decltype(rj)::value, l = l0 + ri;
+                    const real v0 = b0[ri], v1 = b1[ri], v2 = b2[ri];
+                    const real x0 = fma(S.s[0][0], v0, fma(S.s[0][1], v1, S.s[0][2] * v2));
+                    const real x1 = fma(S.s[1][0], v0, fma(S.s[1][1], v1, S.s[1][2] * v2));
+                    const real x2 = fma(S.s[2][0], v0, fma(S.s[2][1], v1, S.s[2][2] * v2));
+                    if constexpr (KTILDE) KtCol<N, l>::apply(x0, x1, x2, acc);
+                    else KhCol<N, l>::apply(x0, x1, x2, acc);
+                });
+            }
+            __builtin_amdgcn_sched_barrier(0);
         });
         lds_sync();
     });
@@ -327,13 +349,42 @@ __device__ __forceinline__ void flux_lift(const Lane<real> &L, const double *A, 
     });
 }
 
-// col[m] <- sum_n f^h[m][n] col[n] for one face-basis column in LDS (f^h is
-// block diagonal by degree, applied one block at a time).
-template <int N, typename real>
+// Face rows in parts of whole degree blocks (degree d holds rows
+// [d(d+1)/2, (d+1)(d+2)/2)), each part at most fpr rows.  With fpr = 16 the
+// own and the neighbour rows of one part fit side by side in one LDS chunk
+// (used in FP64, where a second chunk buffer would halve occupancy).
+template <typename real>
+constexpr int FPR = sizeof(real) == 8 ? 16 : 64;
+__host__ __device__ constexpr int face_parts(int n, int fpr)
+{
+    int parts = 1, rows = 0;
+    for (int d = 0; d <= n; ++d) {
+        if (rows + d + 1 > fpr) { ++parts; rows = 0; }
+        rows += d + 1;
+    }
+    return parts;
+}
+// first degree of part i (the last part ends at degree n + 1)
+__host__ __device__ constexpr int face_part_d0(int n, int fpr, int i)
+{
+    int part = 0, rows = 0;
+    for (int d = 0; d <= n; ++d) {
+        if (rows + d + 1 > fpr) { ++part; rows = 0; }
+        if (part == i && rows == 0) return d;
+        rows += d + 1;
+    }
+    return n + 1;
+}
+
+// col[m - M0] <- sum_n f^h[m][n] col[n - M0] for the degree blocks
+// [D0, D1) of one face-basis column in LDS (rows from M0 = D0(D0+1)/2 on);
+// f^h is block diagonal by degree and is applied one block at a time.
+template <int N, int D0, int D1, typename real>
 __device__ __forceinline__ void orient_column(real *col, int h)
 {
-    static_for<0, N + 1>([&](auto di) {
-        constexpr int d = decltype(di)::value, off = d * (d + 1) / 2;
+    constexpr int M0 = D0 * (D0 + 1) / 2;
+    static_for<D0, D1>([&](auto di) {
+        constexpr int d = decltype(di)::value, off = d * (d + 1) / 2 - M0;
         real in[d + 1], out[d + 1];
 #pragma unroll
         for (int i = 0; i < d + 1; ++i) in[i] = col[off + i];
@@ -345,19 +396,19 @@ __device__ __forceinline__ void orient_column(real *col, int h)
     });
 }
 
-// Both flux terms of face S with one lift:
+// Both flux terms of face S, rows [M0, M0+CNT) of the face basis, with one
+// lift:
 // acc[k] += sum_m Rh^S[k][m] sum_q (Ap[p][q] Xo[m][q] + Am[p][q] Xn[m][q]),
-// with all Bf rows of the own traces Xo and of the (already oriented)
-// neighbour traces Xn in LDS (columns of xo_buf and xn_buf, row stride LB).
-// The local and neighbour terms are lifted by the same matrix, so summing
-// before the lift halves the lift work.  MIX: the sum runs in FP64 and is
-// rounded once before the FP32 lift.
-template <int N, int S, bool MIX = false, typename real>
+// with those rows of the own traces Xo and of the (already oriented)
+// neighbour traces Xn in LDS (columns of xo_buf and xn_buf, row m at m - M0,
+// row stride LB).  The local and neighbour terms are lifted by the same
+// matrix, so summing before the lift halves the lift work.  MIX: the sum
+// runs in FP64 and is rounded once before the FP32 lift.
+template <int N, int S, bool MIX, int M0, int CNT, typename real>
 __device__ __forceinline__ void flux_lift_pair(const Lane<real> &L, const double *Ap, const double *Am,
                                                const real *xo_buf, const real *xn_buf, real *acc)
 {
     using mreal = typename std::conditional<MIX, double, real>::type;
-    static_assert(nb2(N) <= CH<real>, "face rows must fit one chunk");
     mreal ap[NQ], am[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -366,15 +417,20 @@ __device__ __forceinline__ void flux_lift_pair(const Lane<real> &L, const double
     }
     const real *xo = xo_buf + L.e * NQ * LB<real>;
     const real *xn = xn_buf + L.e * NQ * LB<real>;
-    static_for<0, nb2(N)>([&](auto mi) {
-        constexpr int m = decltype(mi)::value;
-        mreal g = ap[0] * (mreal)xo[m];
+    static_for<0, (CNT + SB - 1) / SB>([&](auto bi) {
+        constexpr int r0 = decltype(bi)::value * SB, rn = (CNT - r0) < SB ? (CNT - r0) : SB;
+        if (code_block<real>()) {
+            static_for<0, rn>([&](auto rj) {
+                constexpr int r = r0 + decltype(rj)::value;
+                mreal g = ap[0] * (mreal)xo[r];
 #pragma unroll
-        for (int q = 1; q < NQ; ++q) g = fma(ap[q], (mreal)xo[q * LB<real> + m], g);
+                for (int q = 1; q < NQ; ++q) g = fma(ap[q], (mreal)xo[q * LB<real> + r], g);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) g = fma(am[q], (mreal)xn[q * LB<real> + m], g);
-        RhCol<N, S, m>::apply((real)g, acc);
-        row_fence<m>();
+                for (int q = 0; q < NQ; ++q) g = fma(am[q], (mreal)xn[q * LB<real> + r], g);
+                RhCol<N, S, M0 + r>::apply((real)g, acc);
+            });
+        }
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -384,7 +440,16 @@ __device__ __forceinline__ void face_trace(const real *I, real *tr)
     constexpr int B = nb3(N), Bf = nb2(N);
 #pragma unroll
     for (int m = 0; m < Bf; ++m) tr[m] = real(0);
-    static_for<0, B>([&](auto li) { RCol<N, S, decltype(li)::value>::apply(I[decltype(li)::value], tr); });
+    static_for<0, (B + 7) / 8>([&](auto bi) {
+        constexpr int l0 = decltype(bi)::value * 8, ln = (B - l0) < 8 ? (B - l0) : 8;
+        if (code_block<real>()) {
+            static_for<0, ln>([&](auto lj) {
+                constexpr int l = l0 + decltype(lj)::value;
+                RCol<N, S, l>::apply(I[l], tr);
+            });
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
 template <int N, typename real>
