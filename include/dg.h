@@ -25,7 +25,15 @@
  *     T         [E][N+1][9][B]     Taylor-scaled time derivatives
  *                                  T^d = dt^d/d! * D^d  (rows of T^d at or
  *                                  beyond C(N-d+3,3) are written as 0)
- *     traces    [E][4][9][Bf]      face traces R^s^T I of every element
+ *     traces    [E][4][9*Bf]       face traces R^s^T I of every element; one
+ *                                  face block holds the face basis in parts
+ *                                  of whole degree blocks, one part after the
+ *                                  other, each part quantity major
+ *                                  ([9][rows of the part]).  FP32 and mixed
+ *                                  plans use one part ([9][Bf]); FP64 plans
+ *                                  split the face basis into parts of at most
+ *                                  16 rows (degree 5: rows [0,15), [15,21);
+ *                                  degree 6: [0,15), [15,28)).
  *     star_packed [E][9][3][3]     star matrices in packed form (see
  *                                  dg_pack_star), element type of the plan
  *     Aplus, Aminus [E][4][9][9]   flux-solver matrices, FP64, row major
@@ -155,7 +163,9 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
 /* The two launches of one dg_step, exposed separately so that a caller can
  * place work (for instance an exchange of partition-boundary traces) between
  * them.  dg_step_predict: I = time integral of the predictor of Q and
- * traces[e][s] = R^s^T I[e].  dg_step_correct: Q += volume + local flux +
+ * traces[e][s] = R^s^T I[e] (face block layout above; a face block is
+ * contiguous, so it can be exchanged as one piece).  dg_step_correct: Q +=
+ * volume + local flux +
  * neighbour flux, the local and neighbour terms read from `traces`. */
 int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, const void *star_packed,
                     void *I, void *traces, hipStream_t stream);

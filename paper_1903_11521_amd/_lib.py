@@ -231,7 +231,9 @@ class Plan:
         return (E, 9, self.B)
 
     def trace_shape(self, E):
-        return (E, 4, 9, self.Bf)
+        """Face-trace work array: one contiguous block of 9*Bf values per
+        element and face (internal layout: see include/dg.h)."""
+        return (E, 4, 9 * self.Bf)
 
     def deriv_shape(self, E):
         return (E, self.degree + 1, 9, self.B)
@@ -350,7 +352,7 @@ class Batch:
             chk = Plan._check_tensor
             arr[i] = BatchItem(N, E, float(m["dt"]),
                                chk(m["Q"], (E, 9, B), dt_, "Q"), chk(m["I"], (E, 9, B), dt_, "I"),
-                               chk(m["traces"], (E, 4, 9, Bf), dt_, "traces"),
+                               chk(m["traces"], (E, 4, 9 * Bf), dt_, "traces"),
                                chk(m["star_packed"], (E, 9, 3, 3), dt_, "star_packed"),
                                chk(m["Aplus"], (E, 4, 9, 9), torch.float64, "Aplus"),
                                chk(m["Aminus"], (E, 4, 9, 9), torch.float64, "Aminus"),

@@ -250,6 +250,17 @@ __device__ __forceinline__ void store_columns(const Lane<real> &L, EPtr eptr, co
     });
 }
 
+// store rows [M0, M0+CNT) of this lane's register column to rows [0, CNT) of
+// element blocks whose columns are CNT apart (one part of a face block)
+template <int M0, int CNT, typename real, typename EPtr>
+__device__ __forceinline__ void store_part(const Lane<real> &L, EPtr eptr, const real *src, int64_t E)
+{
+    static_for<0, CNT>([&](auto ri) { L.own[ri] = src[M0 + decltype(ri)::value]; });
+    lds_sync();
+    chunk_store<CNT, CNT>(L, eptr, 0, E);
+    lds_sync();
+}
+
 // Q(own column) += acc, rows [0,B)
 template <int B, typename real>
 __device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const real *acc, int64_t E)

@@ -135,7 +135,7 @@ def test_edge_sizes(E):
     if E == 0:
         Q = torch.zeros((0, 9, plan.B), dtype=torch.float64, device="cuda:0")
         I = torch.zeros_like(Q)
-        tr = torch.zeros((0, 4, 9, plan.Bf), dtype=torch.float64, device="cuda:0")
+        tr = torch.zeros(plan.trace_shape(0), dtype=torch.float64, device="cuda:0")
         z = lambda *s, dt=torch.float64: torch.zeros(s, dtype=dt, device="cuda:0")
         plan.step(Q, I, tr, z(0, 9, 3, 3), z(0, 4, 9, 9), z(0, 4, 9, 9), z(0, 4, dt=torch.int32),
                   z(0, 4, dt=torch.uint8), 0.1, 2)
