@@ -151,7 +151,7 @@ template <int CNT>
 struct RowSplit {
     static constexpr int K = (CNT + 7) / 8;          // rows per lane and column
     static constexpr int TAIL = CNT - 8 * (K - 1);   // lanes s < TAIL own row 8(K-1)+s
-    static constexpr int GQ = (8 + K - 1) / K;       // columns per load group (about 8 loads in flight)
+    static constexpr int GQ = (40 + K - 1) / K;       // columns per load group (about 40 loads in flight)
 };
 
 // Cooperative load of rows [l0, l0+CNT) of the 9 columns of every element
