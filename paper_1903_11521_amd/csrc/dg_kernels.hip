@@ -151,44 +151,70 @@ template <int CNT>
 struct RowSplit {
     static constexpr int K = (CNT + 7) / 8;          // rows per lane and column
     static constexpr int TAIL = CNT - 8 * (K - 1);   // lanes s < TAIL own row 8(K-1)+s
-    static constexpr int GQ = (40 + K - 1) / K;       // columns per load group (about 40 loads in flight)
 };
 
-// Cooperative load of rows [l0, l0+CNT) of the 9 columns of every element
-// slot into LDS (slot g, column q, row r at buf[(g*NQ + q)*LB + r]).
-// eptr(g) is the global address of row 0 of column 0 of slot g's element
-// block, whose columns are QS apart, or null for zeros.  Branch free: in the
-// last row of a column, lanes past the chunk re-read its row 0 and write
-// rows [CNT, 8K) of their LDS column, which nothing reads (8K <= LB).
+// One chunk of element data in flight: rows [l0, l0+CNT) of the 9 columns of
+// this lane's element slot, K values per column.
+template <int CNT, typename real>
+struct ChunkRegs {
+    real v[NQ][RowSplit<CNT>::K];
+};
+
+// Issue the loads of a chunk (rows [l0, l0+CNT) of the 9 columns of every
+// element slot).  eptr(g) is the global address of row 0 of column 0 of slot
+// g's element block, whose columns are QS apart, or null for zeros.  All
+// loads of the chunk are in flight together.  Branch free: in the last row
+// of a column, lanes past the chunk re-read its row 0 (chunk_put then writes
+// them to rows [CNT, 8K) of their LDS column, which nothing reads).
 template <int CNT, int QS, typename real, typename EPtr>
-__device__ __forceinline__ void chunk_load(const Lane<real> &L, EPtr eptr, int l0)
+__device__ __forceinline__ ChunkRegs<CNT, real> chunk_fetch(const Lane<real> &L, EPtr eptr, int l0)
 {
     using RS = RowSplit<CNT>;
-    constexpr int K = RS::K, GQ = RS::GQ;
+    constexpr int K = RS::K;
     static_assert(8 * K <= LB<real>, "tail rows must stay inside the column slot");
     static_assert(9 * QS <= 1024, "element block longer than the zero block");
     const int g = L.lane >> 3, s = L.lane & 7;
     const real *e0 = eptr(g);
     const real *src = (e0 ? e0 : reinterpret_cast<const real *>(dg_zero_block)) + l0 + s;
     const real *srct = s < RS::TAIL ? src + 8 * (K - 1) : src - s;   // last row, else row 0
-    real *dst = L.buf + g * NQ * LB<real> + s;
-    static_for<0, (NQ + GQ - 1) / GQ>([&](auto gi) {
-        constexpr int q0 = decltype(gi)::value * GQ, nq = (NQ - q0) < GQ ? (NQ - q0) : GQ;
-        real v[nq][K];
-        static_for<0, nq>([&](auto ji) {
-            static_for<0, K>([&](auto ki) {
-                constexpr int j = decltype(ji)::value, kk = decltype(ki)::value;
-                v[j][kk] = kk < K - 1 ? src[(q0 + j) * QS + 8 * kk] : srct[(q0 + j) * QS];
-            });
+    ChunkRegs<CNT, real> r;
+    static_for<0, NQ>([&](auto qi) {
+        static_for<0, K>([&](auto ki) {
+            constexpr int q = decltype(qi)::value, kk = decltype(ki)::value;
+            r.v[q][kk] = kk < K - 1 ? src[q * QS + 8 * kk] : srct[q * QS];
         });
-        static_for<0, nq>([&](auto ji) {
-            static_for<0, K>([&](auto ki) {
-                constexpr int j = decltype(ji)::value, kk = decltype(ki)::value;
-                dst[(q0 + j) * LB<real> + 8 * kk] = v[j][kk];
-            });
-        });
-        __builtin_amdgcn_sched_barrier(0);   // one group of loads in flight at a time
     });
+    return r;
+}
+
+// Two fetched chunks (own and neighbour face rows of the corrector).
+template <int CNT, typename real>
+struct ChunkPair {
+    ChunkRegs<CNT, real> xo, xn;
+};
+
+// Write a fetched chunk to LDS (slot g, column q, row r at
+// buf[(g*NQ + q)*LB + r]).
+template <int CNT, typename real>
+__device__ __forceinline__ void chunk_put(const Lane<real> &L, const ChunkRegs<CNT, real> &r)
+{
+    constexpr int K = RowSplit<CNT>::K;
+    const int g = L.lane >> 3, s = L.lane & 7;
+    real *dst = L.buf + g * NQ * LB<real> + s;
+    static_for<0, NQ>([&](auto qi) {
+        static_for<0, K>([&](auto ki) {
+            constexpr int q = decltype(qi)::value, kk = decltype(ki)::value;
+            dst[q * LB<real> + 8 * kk] = r.v[q][kk];
+        });
+    });
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Cooperative load of a chunk into LDS: one memory round trip.
+template <int CNT, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void chunk_load(const Lane<real> &L, EPtr eptr, int l0)
+{
+    chunk_put<CNT>(L, chunk_fetch<CNT, QS>(L, eptr, l0));
 }
 
 // Cooperative store of rows [l0, l0+CNT) of the columns of the real
