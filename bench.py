@@ -274,15 +274,16 @@ def main():
     neigh, face_rot = to(mesh.neigh), to(mesh.face_rot)
     I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device=dev)
     tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device=dev)
+    tr2 = torch.empty_like(tr)      # second trace array: one launch per step
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     log("warmup %d steps" % args.warmup)
-    plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.warmup)
+    plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.warmup, traces_b=tr2)
     plan.sync()
     log("timed %d steps on %d elements" % (args.steps, E))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.steps)
+    plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.steps, traces_b=tr2)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -290,22 +291,27 @@ def main():
 
     # per-kernel launch durations with HIP events on the launch stream
     log("per-kernel event timing")
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # (the timed region is one predictor, steps-1 fused launches, one corrector)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for k in range(args.steps):
         ev[k][0].record(stream)
         plan.step_predict(Qg, star_p, dt, I, tr)
         ev[k][1].record(stream)
-        plan.step_correct(I, tr, star_p, Apg, Amg, neigh, face_rot, Qg)
+        plan.step_fused(Qg, I, tr, tr2, star_p, Apg, Amg, neigh, face_rot, dt)
         ev[k][2].record(stream)
+        plan.step_correct(I, tr2, star_p, Apg, Amg, neigh, face_rot, Qg)
+        ev[k][3].record(stream)
     torch.cuda.synchronize()
-    t_pred = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)])) * 1e-3
-    t_corr = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)])) * 1e-3
+    mean_ms = lambda a, b: float(np.mean([ev[k][a].elapsed_time(ev[k][b]) for k in range(args.steps)])) * 1e-3
+    t_pred, t_fused, t_corr = mean_ms(0, 1), mean_ms(1, 2), mean_ms(2, 3)
     itemsize = 8 if prec == dg.DG_FP64 else 4
     counts = np.bincount(mesh.orient.ravel(), minlength=3) / mesh.orient.size
     fm = dg.flop_model(N, counts)
     bm = dg.byte_model(N, itemsize)
-    kern = "step_correct" if t_corr >= t_pred else "step_predict"
-    tk = max(t_corr, t_pred)
+    if plan.fuses_steps and args.steps > 1:
+        kern, tk = "step_fused", t_fused
+    else:
+        kern, tk = max((("step_correct", t_corr), ("step_predict", t_pred)), key=lambda kt: kt[1])
     flops, nbytes = fm[kern] * E, bm[kern] * E
     peak_flops = PEAK_FP64_TFLOPS if prec == dg.DG_FP64 else 78.6   # VALU FMA (no packed FP32)
     ridge = peak_flops * 1e12 / (PEAK_HBM_GBS * 1e9)
@@ -327,11 +333,14 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "elastic ADER-DG, degree %d (B=%d), %dx%dx%dx6 = %d-element jittered periodic "
-                               "cube-split mesh, random materials, %d time steps" % (N, plan.B, args.n, args.n,
-                                                                                     args.n, E, args.steps),
+                               "cube-split mesh, random materials, %d time steps, %s" % (
+                                   N, plan.B, args.n, args.n, args.n, E, args.steps,
+                                   "one launch per step (corrector fused with the next predictor)"
+                                   if plan.fuses_steps else "predictor and corrector launch per step"),
                    "elements": E, "degree": N, "dt": dt},
         "useful_gflops": step_flops * args.steps / elapsed / 1e9,
-        "kernel_ms": {"step_predict": t_pred * 1e3, "step_correct": t_corr * 1e3},
+        "kernel_ms": dict({"step_predict": t_pred * 1e3, "step_correct": t_corr * 1e3},
+                          **({"step_fused": t_fused * 1e3} if plan.fuses_steps else {})),
         "roofline": roof,
         "paper_context": "paper's best single-simulation O6 DP CPU figure: 1244 MDoF/s on 2x Xeon 8174 "
                          "(about 2.47 M element-updates/s); context, not the target",

@@ -116,6 +116,10 @@ int dg_plan_create(int degree, dg_precision precision, dg_plan **out);
 int dg_plan_destroy(dg_plan *plan);
 /* B and Bf of a plan (either pointer may be NULL). */
 int dg_plan_sizes(const dg_plan *plan, int *B, int *Bf);
+/* 1 if this plan runs dg_step_fused (and dg_step with a second trace array)
+ * as one fused launch, 0 if as two launches (the faster choice, measured on
+ * MI355X: fused from degree 2 to 3); negative status on a null plan. */
+int dg_plan_fuses_steps(const dg_plan *plan);
 const char *dg_last_error(void);
 
 /* ---- device compute calls (stream ordered) ----------------------------- */
@@ -153,12 +157,17 @@ int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I
 
 /* n_steps global time steps of the full scheme (predictor, time integral,
  * volume, local and neighbour flux) on all E elements, Q updated in place.
- * I [E][9][B] and traces [E][4][9][Bf] are caller-provided work arrays; on
+ * I [E][9][B] and traces [E][4][9*Bf] are caller-provided work arrays; on
  * return they hold the time integral and face traces of the last step.
- * Neighbour indices must lie in [0, E); others are treated like -1. */
+ * traces_b (same size as traces, or NULL) is a second trace array.  With it,
+ * and where dg_plan_fuses_steps says so, step k's corrector and step k+1's
+ * predictor run as one launch (one launch per step; the traces alternate
+ * between the two arrays, because neighbours still read step k's traces
+ * while step k+1's are written).  Otherwise each step is two launches.  All
+ * give the same result bit for bit.  Neighbour indices must lie in [0, E); others are treated like -1. */
 int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
-            const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
-            const uint8_t *face_rot, hipStream_t stream);
+            void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
+            const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
 
 /* The two launches of one dg_step, exposed separately so that a caller can
  * place work (for instance an exchange of partition-boundary traces) between
@@ -172,6 +181,18 @@ int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, co
 int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *traces,
                     const void *star_packed, const double *Aplus, const double *Aminus,
                     const int32_t *neigh, const uint8_t *face_rot, void *Q, hipStream_t stream);
+
+/* The launch between them in a fused dg_step: the corrector of step k
+ * (reading I and the step-k traces in traces_in; Q += volume + local flux +
+ * neighbour flux) followed, per element in the same launch, by the predictor
+ * of step k+1 on the updated Q (I overwritten with step k+1's time integral,
+ * its traces written to traces_out, which must not be traces_in: neighbours
+ * still read traces_in).  dg_step_predict, then n-1 dg_step_fused with the
+ * trace arrays swapped after each, then dg_step_correct, is n steps.  Where
+ * dg_plan_fuses_steps is 0 the two halves run as two launches. */
+int dg_step_fused(const dg_plan *plan, int64_t E, double dt, void *Q, void *I, const void *traces_in,
+                  void *traces_out, const void *star_packed, const double *Aplus, const double *Aminus,
+                  const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
 
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 

@@ -60,7 +60,9 @@ def _load():
         lib.dg_volume.argtypes = [vp, i64, vp, vp, vp, vp]
         lib.dg_local_flux.argtypes = [vp, i64, vp, vp, vp, vp]
         lib.dg_neighbour_flux.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
-        lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_plan_fuses_steps.argtypes = [vp]
         lib.dg_step_predict.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp]
         lib.dg_step_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_sync.argtypes = [vp]
@@ -147,12 +149,14 @@ def flop_model(degree: int, orient_counts=None) -> dict:
     predict = ck + ti + traces
     correct = vol + 2 * (lift + mix) + fh
     return dict(ck=ck, ti=ti, traces=traces, volume=vol, local=lift + mix, neighbour=lift + mix + fh,
-                step_predict=predict, step_correct=correct, step=predict + correct, B=B, Bf=Bf)
+                step_predict=predict, step_correct=correct, step=predict + correct, step_fused=predict + correct,
+                B=B, Bf=Bf)
 
 
 def byte_model(degree: int, itemsize: int = 8) -> dict:
-    """Algorithmic HBM bytes per element of the two step kernels: every array
-    read or written once (neighbour traces with ideal reuse); A+/A- FP64."""
+    """Algorithmic HBM bytes per element of the step kernels: every array read
+    or written once (neighbour traces with ideal reuse); A+/A- FP64.
+    step_fused is the corrector of one step with the predictor of the next."""
     N = degree
     B, Bf = comb(N + 3, 3), comb(N + 2, 2)
     q = 9 * B * itemsize
@@ -162,7 +166,8 @@ def byte_model(degree: int, itemsize: int = 8) -> dict:
     tables = 4 * 4 + 4
     predict = q + star + q + tr                      # Q, star -> I, traces
     correct = q + tr + tr + star + flux + tables + q + q   # I, own+nbr traces, star, A+-, tables, Q rw
-    return dict(step_predict=predict, step_correct=correct, step=predict + correct)
+    fused = correct + q + tr                         # + next I and traces (Q, star read once)
+    return dict(step_predict=predict, step_correct=correct, step=predict + correct, step_fused=fused)
 
 
 # ---------------------------------------------------------------------------
@@ -186,6 +191,7 @@ class Plan:
         B, Bf = ctypes.c_int(), ctypes.c_int()
         _check(lib.dg_plan_sizes(h, ctypes.byref(B), ctypes.byref(Bf)))
         self.B, self.Bf = B.value, Bf.value
+        self.fuses_steps = bool(_load().dg_plan_fuses_steps(self._h))
         torch = _torch()
         self.dtype = torch.float64 if precision == DG_FP64 else torch.float32
 
@@ -293,13 +299,17 @@ class Plan:
                                          self._t(Q, self.dof_shape(E), self.dtype, "Q"), self._stream(stream)))
         return Q
 
-    def step(self, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, dt, n_steps=1, stream=None):
+    def step(self, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, dt, n_steps=1, stream=None,
+             traces_b=None):
+        """n_steps time steps; with a second trace array traces_b, one launch
+        per step (corrector and next predictor fused)."""
         torch = _torch()
         E = Q.shape[0]
+        tb = None if traces_b is None else self._t(traces_b, self.trace_shape(E), self.dtype, "traces_b")
         _check(_load().dg_step(self._h, E, float(dt), int(n_steps),
                                self._t(Q, self.dof_shape(E), self.dtype, "Q"),
                                self._t(I, self.dof_shape(E), self.dtype, "I"),
-                               self._t(traces, self.trace_shape(E), self.dtype, "traces"),
+                               self._t(traces, self.trace_shape(E), self.dtype, "traces"), tb,
                                self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
                                self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
                                self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
@@ -314,6 +324,20 @@ class Plan:
                                        self._t(I, self.dof_shape(E), self.dtype, "I"),
                                        self._t(traces, self.trace_shape(E), self.dtype, "traces"),
                                        self._stream(stream)))
+
+    def step_fused(self, Q, I, traces_in, traces_out, star_packed, Aplus, Aminus, neigh, face_rot, dt,
+                   stream=None):
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_step_fused(self._h, E, float(dt), self._t(Q, self.dof_shape(E), self.dtype, "Q"),
+                                     self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                     self._t(traces_in, self.trace_shape(E), self.dtype, "traces_in"),
+                                     self._t(traces_out, self.trace_shape(E), self.dtype, "traces_out"),
+                                     self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                     self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                                     self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                                     self._t(neigh, (E, 4), torch.int32, "neigh"),
+                                     self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
 
     def step_correct(self, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, Q, stream=None):
         torch = _torch()

@@ -6,6 +6,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -213,8 +214,8 @@ int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I
 }
 
 int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
-            const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
-            const uint8_t *face_rot, hipStream_t s)
+            void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
+            const int32_t *neigh, const uint8_t *face_rot, hipStream_t s)
 {
     CHECK_PLAN(plan);
     CHECK_E(E);
@@ -222,18 +223,40 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
     CHECK_PTR(E, Q, "Q");
     CHECK_PTR(E, I, "I");
     CHECK_PTR(E, traces, "traces");
+    if (traces_b && (reinterpret_cast<uintptr_t>(traces_b) & 15))
+        return fail(DG_EINVAL, "traces_b is not 16-byte aligned%s", "");
+    if (traces_b && E > 0 && traces_b == traces) return fail(DG_EINVAL, "traces_b must not be traces%s", "");
     CHECK_PTR(E, star_packed, "star_packed");
     CHECK_PTR(E, Aplus, "Aplus");
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
-    const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
-    for (int n = 0; n < n_steps; ++n) {
-        hipError_t e = plan->tab.step_predict(it, s);
-        if (e != hipSuccess) return hip_status(e, "dg_step (predict)");
-        e = plan->tab.step_correct(it, s);
-        if (e != hipSuccess) return hip_status(e, "dg_step (correct)");
+    if (!traces_b || n_steps < 2 || !plan->tab.fuse_step) {
+        const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
+        for (int n = 0; n < n_steps; ++n) {
+            hipError_t e = plan->tab.step_predict(it, s);
+            if (e != hipSuccess) return hip_status(e, "dg_step (predict)");
+            e = plan->tab.step_correct(it, s);
+            if (e != hipSuccess) return hip_status(e, "dg_step (correct)");
+        }
+        return DG_OK;
     }
+    // predictor of step 1, then n-1 fused launches (corrector of step k and
+    // predictor of step k+1), then the corrector of step n.  The traces
+    // alternate between the two buffers; the first is chosen so that the
+    // last step's traces end up in `traces`.
+    void *cur = (n_steps & 1) ? traces : traces_b, *nxt = (n_steps & 1) ? traces_b : traces;
+    DgItem it = make_item(E, dt, Q, I, cur, star_packed, Aplus, Aminus, neigh, face_rot);
+    hipError_t e = plan->tab.step_predict(it, s);
+    if (e != hipSuccess) return hip_status(e, "dg_step (predict)");
+    for (int n = 1; n < n_steps; ++n) {
+        e = plan->tab.step_fused(it, nxt, s);
+        if (e != hipSuccess) return hip_status(e, "dg_step (fused)");
+        std::swap(cur, nxt);
+        it.traces = cur;
+    }
+    e = plan->tab.step_correct(it, s);
+    if (e != hipSuccess) return hip_status(e, "dg_step (correct)");
     return DG_OK;
 }
 
@@ -268,6 +291,37 @@ int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *t
     const DgItem it = make_item(E, 0.0, Q, const_cast<void *>(I), const_cast<void *>(traces), star_packed, Aplus,
                                 Aminus, neigh, face_rot);
     return hip_status(plan->tab.step_correct(it, s), "dg_step_correct");
+}
+
+int dg_step_fused(const dg_plan *plan, int64_t E, double dt, void *Q, void *I, const void *traces_in,
+                  void *traces_out, const void *star_packed, const double *Aplus, const double *Aminus,
+                  const int32_t *neigh, const uint8_t *face_rot, hipStream_t s)
+{
+    CHECK_PLAN(plan);
+    CHECK_E(E);
+    CHECK_PTR(E, Q, "Q");
+    CHECK_PTR(E, I, "I");
+    CHECK_PTR(E, traces_in, "traces_in");
+    CHECK_PTR(E, traces_out, "traces_out");
+    if (E > 0 && traces_in == traces_out) return fail(DG_EINVAL, "traces_out must not be traces_in%s", "");
+    CHECK_PTR(E, star_packed, "star_packed");
+    CHECK_PTR(E, Aplus, "Aplus");
+    CHECK_PTR(E, Aminus, "Aminus");
+    CHECK_PTR(E, neigh, "neigh");
+    CHECK_PTR(E, face_rot, "face_rot");
+    DgItem it = make_item(E, dt, Q, I, const_cast<void *>(traces_in), star_packed, Aplus, Aminus, neigh, face_rot);
+    if (plan->tab.fuse_step) return hip_status(plan->tab.step_fused(it, traces_out, s), "dg_step_fused");
+    // same work as two launches
+    hipError_t e = plan->tab.step_correct(it, s);
+    if (e != hipSuccess) return hip_status(e, "dg_step_fused (correct)");
+    it.traces = traces_out;
+    return hip_status(plan->tab.step_predict(it, s), "dg_step_fused (predict)");
+}
+
+int dg_plan_fuses_steps(const dg_plan *plan)
+{
+    CHECK_PLAN(plan);
+    return plan->tab.fuse_step ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,12 @@ struct DgTable {
                                  const double *Am, void *Q, hipStream_t s);
     hipError_t (*step_predict)(const DgItem &it, hipStream_t s);
     hipError_t (*step_correct)(const DgItem &it, hipStream_t s);
+    // corrector of one step and predictor of the next in one launch: reads the
+    // traces in it.traces, writes the next step's traces to tr_out
+    hipError_t (*step_fused)(const DgItem &it, void *tr_out, hipStream_t s);
+    // whether the fused launch is used (it is faster than the two separate
+    // launches only at low degree; measured on MI355X, all precisions)
+    bool fuse_step;
     // batched: items (device array) of one degree; block_item maps each of the
     // nblocks workgroups to its item
     hipError_t (*batch_predict)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);

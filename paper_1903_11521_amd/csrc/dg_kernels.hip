@@ -724,6 +724,7 @@ k_step_predict(int64_t E, double dt, const real *__restrict__ Q, const real *__r
                real *__restrict__ Iout, real *__restrict__ traces)
 {
     const int64_t lb = logical_block();
+    __shared__ real buf[NCOL * LB<real>];
 #include "step_predict_body.inc"
 }
 
@@ -734,7 +735,46 @@ k_step_correct(int64_t E, const real *__restrict__ Iin, const real *__restrict__
                const int32_t *__restrict__ neigh, const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
 {
     const int64_t lb = logical_block();
+    __shared__ real buf[NCOL * LB<real>];
 #include "step_correct_body.inc"
+}
+
+// Fused step: the corrector of step n (reads I^n and the face traces of step
+// n from tr_in, updates Q) followed, in the same workgroup, by the predictor
+// of step n+1 on the updated Q (writes I^{n+1} over I^n and the traces of
+// step n+1 to tr_out).  I is element local, so it is updated in place; the
+// traces are read by neighbours and so go to the other buffer.  One launch per
+// time step; Q^{n+1} is read back while still in cache.
+template <int N, bool MIX, typename real>
+__global__ void __launch_bounds__(64)
+k_step_fused(int64_t E, double dt, real *__restrict__ I, const real *__restrict__ tr_in,
+             real *__restrict__ tr_out, const real *__restrict__ star, const double *__restrict__ Ap,
+             const double *__restrict__ Am, const int32_t *__restrict__ neigh,
+             const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
+{
+    const int64_t lb = logical_block();
+    __shared__ real buf[NCOL * LB<real>];
+    {
+        const real *Iin = I, *traces = tr_in;
+#include "step_correct_body.inc"
+    }
+    // this wave's stores of Q^{n+1} complete before it reads them back
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    lds_sync();
+    // Opaque copies of the base pointers for the predictor, so that address
+    // arithmetic of the corrector is not kept alive across both phases.  The
+    // pointers escape into the asm and it clobbers memory, so the corrector's
+    // stores of Q stay before it and the predictor's loads after it.
+    real *Ip = I, *Qp = Q;
+    const real *Sp = star;
+    asm volatile("" : "+s"(Ip), "+s"(Qp), "+s"(Sp)::"memory");
+    {
+        const real *Q = Qp;
+        const real *star = Sp;
+        real *Iout = Ip;
+        real *traces = tr_out;
+#include "step_predict_body.inc"
+    }
 }
 
 // Batched forms: every workgroup finds its item in block_item[] (items of one
@@ -750,6 +790,7 @@ k_batch_predict(const StepItem<real> *__restrict__ items,
     const double dt = it.dt;
     const real *Q = it.Q, *star = it.star;
     real *Iout = it.I, *traces = it.traces;
+    __shared__ real buf[NCOL * LB<real>];
 #include "step_predict_body.inc"
 }
 
@@ -766,6 +807,7 @@ k_batch_correct(const StepItem<real> *__restrict__ items,
     const int32_t *neigh = it.neigh;
     const uint8_t *face_rot = it.face_rot;
     real *Q = it.Q;
+    __shared__ real buf[NCOL * LB<real>];
 #include "step_correct_body.inc"
 }
 

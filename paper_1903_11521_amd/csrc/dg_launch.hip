@@ -96,6 +96,16 @@ struct Launch {
                            it.neigh, it.face_rot, (real *)it.Q);
         return hipGetLastError();
     }
+    // corrector of step n (traces of step n in it.traces) + predictor of step
+    // n+1 (its traces to tr_out)
+    static hipError_t step_fused(const DgItem &it, void *tr_out, hipStream_t s)
+    {
+        if (it.E == 0) return hipSuccess;
+        hipLaunchKernelGGL((dgk::k_step_fused<N, MIX, real>), dim3(wave_blocks(it.E)), dim3(64), 0, s, it.E, it.dt,
+                           (real *)it.I, (const real *)it.traces, (real *)tr_out, (const real *)it.star, it.Ap,
+                           it.Am, it.neigh, it.face_rot, (real *)it.Q);
+        return hipGetLastError();
+    }
     static hipError_t batch_predict(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s)
     {
         if (nblocks == 0) return hipSuccess;
@@ -120,6 +130,10 @@ struct Launch {
         t->neighbour_flux = neighbour_flux;
         t->step_predict = step_predict;
         t->step_correct = step_correct;
+        t->step_fused = step_fused;
+        // fused launch slower than predictor + corrector from degree 4 on
+        // (larger code and register footprint of the combined kernel)
+        t->fuse_step = N <= 3;
         t->batch_predict = batch_predict;
         t->batch_correct = batch_correct;
     }
@@ -141,6 +155,7 @@ void DG_CAT(dg_table_, DG_DEGREE)(DgTable *fp64, DgTable *fp32, DgTable *mixed)
     mixed->neighbour_flux = Launch<float, true>::neighbour_flux;
     mixed->step_predict = Launch<float, true>::step_predict;
     mixed->step_correct = Launch<float, true>::step_correct;
+    mixed->step_fused = Launch<float, true>::step_fused;
     mixed->batch_predict = Launch<float, true>::batch_predict;
     mixed->batch_correct = Launch<float, true>::batch_correct;
 }

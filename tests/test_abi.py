@@ -77,7 +77,11 @@ def test_plan_argument_errors():
     assert lib.dg_volume(h, 5, None, None, None, None) == -1
     assert b"null pointer" in lib.dg_last_error()
     assert lib.dg_volume(h, 0, None, None, None, None) == 0  # empty input is a no-op
-    assert lib.dg_step(h, 5, 0.1, -1, *([None] * 9)) == -1
+    assert lib.dg_step(h, 5, 0.1, -1, *([None] * 10)) == -1
+    assert lib.dg_step_fused(h, 5, 0.1, *([None] * 10)) == -1
+    assert b"null pointer" in lib.dg_last_error()
+    assert lib.dg_plan_fuses_steps(h) == 1          # degree 3: fused launch
+    assert lib.dg_plan_fuses_steps(None) == -1
     mis = ctypes.c_void_p(8)   # never dereferenced: rejected before any launch
     assert lib.dg_volume(h, 5, mis, mis, mis, None) == -1
     assert b"aligned" in lib.dg_last_error()
@@ -98,3 +102,6 @@ def test_flop_and_byte_models():
     assert 150e3 < f["step"] < 300e3
     b = dg.byte_model(5)
     assert b["step"] > 30e3
+    # the fused launch saves the predictor's reads of Q and star
+    assert b["step_fused"] == b["step"] - 9 * 56 * 8 - 81 * 8
+    assert f["step_fused"] == f["step"]

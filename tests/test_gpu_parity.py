@@ -102,11 +102,13 @@ def test_step_config0(prec):
     assert dgtest.rel_err(Q1, ref) <= TOL[prec]
 
 
-def test_step_multi_relabelled_degree5():
-    """Three steps on a mesh with all 12 neighbour face/orientation cases."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_step_multi_relabelled_degree5(fused):
+    """Three steps on a mesh with all 12 neighbour face/orientation cases
+    (fused: one launch per step, traces alternating between two arrays)."""
     import paper_1903_11521_amd as dg
     N = 5
-    _say("test_step_multi_relabelled_degree5")
+    _say(f"test_step_multi_relabelled_degree5 fused={fused}")
     mesh, mats, Q, dt = dgtest.mesh_inputs(4, N, 2, relabel=True)
     rm = refmat.refmats(N)
     ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
@@ -120,7 +122,7 @@ def test_step_multi_relabelled_degree5():
     I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0")
     tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0")
     plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
-              _dev(mesh.face_rot), dt, 3)
+              _dev(mesh.face_rot), dt, 3, traces_b=torch.empty_like(tr) if fused else None)
     assert dgtest.rel_err(_host(Qg) - Q, ref - Q) <= 1e-12
 
 
@@ -150,9 +152,15 @@ def test_edge_sizes(E):
     Qg = _dev(d["Q"])
     I = torch.empty(plan.dof_shape(E), dtype=torch.float64, device="cuda:0")
     tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
-    plan.step(Qg, I, tr, plan.pack_star(_dev(d["star"])), _dev(d["Ap"]), _dev(d["Am"]), _dev(neigh),
-              _dev(d["face_rot"]), 0.05, 1)
+    args = (plan.pack_star(_dev(d["star"])), _dev(d["Ap"]), _dev(d["Am"]), _dev(neigh), _dev(d["face_rot"]))
+    plan.step(Qg, I, tr, *args, 0.05, 1)
     assert dgtest.rel_err(_host(Qg) - d["Q"], ref - d["Q"]) <= 1e-12
+    # two more steps, fused, against the oracle
+    ref2 = ref
+    for _ in range(2):
+        ref2 = stages.step(rm, 0.05, ref2, d["star"], d["Ap"], d["Am"], neigh, d["nface"], d["orient"])
+    plan.step(Qg, I, tr, *args, 0.05, 2, traces_b=torch.empty_like(tr))
+    assert dgtest.rel_err(_host(Qg) - ref, ref2 - ref) <= 1e-12
 
 
 def test_step_split_equals_step():
@@ -172,6 +180,32 @@ def test_step_split_equals_step():
         plan.step_predict(Qb, args[0], dt, I, tr)
         plan.step_correct(I, tr, args[0], args[1], args[2], args[3], args[4], Qb)
     assert torch.equal(Qa, Qb)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("N", [2, 3, 5, 6])
+def test_fused_step_equals_split(N, prec):
+    """dg_step with a second trace array (corrector and next predictor in one
+    launch) is bitwise the sequence of dg_step_predict + dg_step_correct, for
+    Q and for the last step's traces, with odd and even step counts."""
+    import paper_1903_11521_amd as dg
+    _say(f"test_fused_step_equals_split N={N} prec={prec}")
+    mesh, mats, Q, dt = dgtest.mesh_inputs(3, N, 11, relabel=True)
+    plan = dg.Plan(N, prec)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    args = [plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot)]
+    for n in (2, 3):
+        Qa, Qb = _dev(Q).to(plan.dtype), _dev(Q).to(plan.dtype)
+        Ia, Ib = (torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0") for _ in range(2))
+        ta, tb, tc = (torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0") for _ in range(3))
+        plan.step(Qa, Ia, ta, *args, dt, n, traces_b=tb)
+        for _ in range(n):
+            plan.step_predict(Qb, args[0], dt, Ib, tc)
+            plan.step_correct(Ib, tc, args[0], args[1], args[2], args[3], args[4], Qb)
+        assert torch.equal(Qa, Qb)
+        assert torch.equal(Ia, Ib)
+        assert torch.equal(ta, tc)
 
 
 def test_full_size_config1_sampled():
