@@ -206,6 +206,20 @@ def test_fused_step_equals_split(N, prec):
         assert torch.equal(Qa, Qb)
         assert torch.equal(Ia, Ib)
         assert torch.equal(ta, tc)
+    # the exported launches: predict, fused (one launch or two, per plan), correct
+    Qa, Qb = _dev(Q).to(plan.dtype), _dev(Q).to(plan.dtype)
+    Ia, Ib = (torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0") for _ in range(2))
+    ta, tb, tc = (torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0") for _ in range(3))
+    plan.step_predict(Qa, args[0], dt, Ia, ta)
+    plan.step_fused(Qa, Ia, ta, tb, *args, dt)
+    plan.step_fused(Qa, Ia, tb, ta, *args, dt)
+    plan.step_correct(Ia, ta, *args, Qa)
+    for _ in range(3):
+        plan.step_predict(Qb, args[0], dt, Ib, tc)
+        plan.step_correct(Ib, tc, *args, Qb)
+    assert torch.equal(Qa, Qb)
+    assert torch.equal(ta, tc)
+    assert plan.fuses_steps == (N <= 3)
 
 
 def test_full_size_config1_sampled():
