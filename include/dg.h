@@ -59,7 +59,8 @@
  * reported synchronously and nothing is enqueued.  A failed kernel launch
  * returns DG_EHIP; faults during execution surface from dg_sync.  The text
  * of the last error of the calling thread is available from dg_last_error.
- * Plans are immutable after creation and may be shared between threads.
+ * Plans are immutable after creation (except for dg_plan_tune) and may be
+ * shared between threads.
  */
 #ifndef DG_H
 #define DG_H
@@ -120,6 +121,14 @@ int dg_plan_sizes(const dg_plan *plan, int *B, int *Bf);
  * as one fused launch, 0 if as two launches (the faster choice, measured on
  * MI355X: fused from degree 2 to 3); negative status on a null plan. */
 int dg_plan_fuses_steps(const dg_plan *plan);
+/* Launch-schedule tuner: times dg_step_fused as one fused launch and as two
+ * launches (corrector, then predictor) on E synthetic elements of this
+ * plan's degree and precision, and keeps the faster for this plan.  Returns
+ * 1 (fused) or 0 (two launches), or a negative status.  Allocates and frees
+ * its own device work buffers (about E times the per-element footprint) and
+ * synchronises the stream.  Call it before the plan is shared between
+ * threads; it is the only call that changes a plan.  E in [64, 2^26]. */
+int dg_plan_tune(dg_plan *plan, int64_t E, hipStream_t stream);
 const char *dg_last_error(void);
 
 /* ---- device compute calls (stream ordered) ----------------------------- */

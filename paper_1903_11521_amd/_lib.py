@@ -63,6 +63,7 @@ def _load():
         lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_plan_fuses_steps.argtypes = [vp]
+        lib.dg_plan_tune.argtypes = [vp, i64, vp]
         lib.dg_step_predict.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp]
         lib.dg_step_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_sync.argtypes = [vp]
@@ -194,6 +195,14 @@ class Plan:
         self.fuses_steps = bool(_load().dg_plan_fuses_steps(self._h))
         torch = _torch()
         self.dtype = torch.float64 if precision == DG_FP64 else torch.float32
+
+    def tune(self, E=100_000, stream=None):
+        """Time the fused and the two-launch step schedule on E synthetic
+        elements and keep the faster for this plan; returns fuses_steps."""
+        r = _load().dg_plan_tune(self._h, int(E), self._stream(stream))
+        _check(r if r < 0 else 0)
+        self.fuses_steps = bool(r)
+        return self.fuses_steps
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

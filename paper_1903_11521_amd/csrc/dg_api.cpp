@@ -324,6 +324,87 @@ int dg_plan_fuses_steps(const dg_plan *plan)
     return plan->tab.fuse_step ? 1 : 0;
 }
 
+namespace {
+
+// device work buffers of the tuner, freed on scope exit
+struct TuneBuffers {
+    std::vector<void *> p;
+    ~TuneBuffers()
+    {
+        for (void *q : p) hipFree(q);
+    }
+    void *get(size_t bytes)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return q;
+    }
+};
+
+}  // namespace
+
+int dg_plan_tune(dg_plan *plan, int64_t E, hipStream_t s)
+{
+    CHECK_PLAN(plan);
+    if (E < 64 || E > ((int64_t)1 << 26)) return fail(DG_EINVAL, "tuning size %s%lld outside [64, 2^26]", "", E);
+    const size_t rs = plan->prec == DG_FP64 ? 8 : 4;
+    const size_t nq = (size_t)E * 9 * plan->B, ntr = (size_t)E * 4 * 9 * plan->Bf;
+    TuneBuffers b;
+    void *Q = b.get(nq * rs), *I = b.get(nq * rs), *t0 = b.get(ntr * rs), *t1 = b.get(ntr * rs);
+    void *star = b.get((size_t)E * 81 * rs);
+    double *Ap = (double *)b.get((size_t)E * 4 * 81 * 8), *Am = (double *)b.get((size_t)E * 4 * 81 * 8);
+    int32_t *neigh = (int32_t *)b.get((size_t)E * 4 * 4);
+    uint8_t *rot = (uint8_t *)b.get((size_t)E * 4);
+    if (!Q || !I || !t0 || !t1 || !star || !Ap || !Am || !neigh || !rot)
+        return fail(DG_ENOMEM, "out of device memory%s for tuning", "");
+    // zero data (kernel time does not depend on the values) on a neighbour
+    // pattern with the reach of a structured mesh: faces point 1, 7, E/64 and
+    // E/8 elements away
+    std::vector<int32_t> nb((size_t)E * 4);
+    const int64_t off[4] = {1, 7, E / 64 + 1, E / 8 + 1};
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) nb[e * 4 + f] = (int32_t)((e + off[f]) % E);
+    hipError_t e = hipMemcpyAsync(neigh, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, s);
+    for (void *z : {Q, I, t0, t1, star}) {
+        if (e == hipSuccess) e = hipMemsetAsync(z, 0, z == star ? (size_t)E * 81 * rs : (z == Q || z == I) ? nq * rs : ntr * rs, s);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(Ap, 0, (size_t)E * 4 * 81 * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(Am, 0, (size_t)E * 4 * 81 * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(rot, 0, (size_t)E * 4, s);
+    if (e != hipSuccess) return hip_status(e, "dg_plan_tune (setup)");
+    const DgItem it = make_item(E, 1e-3, Q, I, t0, star, Ap, Am, neigh, rot);
+    hipEvent_t ev[3];
+    for (auto &x : ev)
+        if ((e = hipEventCreate(&x)) != hipSuccess) return hip_status(e, "dg_plan_tune (events)");
+    auto run = [&](bool fused) -> hipError_t {
+        if (fused) return plan->tab.step_fused(it, t1, s);
+        hipError_t r = plan->tab.step_correct(it, s);
+        if (r == hipSuccess) {
+            DgItem i2 = it;
+            i2.traces = t1;
+            r = plan->tab.step_predict(i2, s);
+        }
+        return r;
+    };
+    // warm both, then alternate 4 timed rounds of each; keep the faster total
+    float tot[2] = {0.f, 0.f};
+    for (int rep = -1; rep < 4 && e == hipSuccess; ++rep)
+        for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+            e = hipEventRecord(ev[0], s);
+            if (e == hipSuccess) e = run(v == 1);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (rep >= 0) tot[v] += ms;
+        }
+    for (auto &x : ev) hipEventDestroy(x);
+    if (e != hipSuccess) return hip_status(e, "dg_plan_tune");
+    plan->tab.fuse_step = tot[1] < tot[0];
+    return plan->tab.fuse_step ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------

@@ -82,6 +82,9 @@ def test_plan_argument_errors():
     assert b"null pointer" in lib.dg_last_error()
     assert lib.dg_plan_fuses_steps(h) == 1          # degree 3: fused launch
     assert lib.dg_plan_fuses_steps(None) == -1
+    assert lib.dg_plan_tune(None, 1000, None) == -1
+    assert lib.dg_plan_tune(h, 10, None) == -1      # tuning size out of range, rejected before any allocation
+    assert b"tuning size" in lib.dg_last_error()
     mis = ctypes.c_void_p(8)   # never dereferenced: rejected before any launch
     assert lib.dg_volume(h, 5, mis, mis, mis, None) == -1
     assert b"aligned" in lib.dg_last_error()

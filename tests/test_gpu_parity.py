@@ -222,6 +222,32 @@ def test_fused_step_equals_split(N, prec):
     assert plan.fuses_steps == (N <= 3)
 
 
+@pytest.mark.parametrize("N", [3, 5])
+def test_plan_tune(N):
+    """The launch-schedule tuner picks one of the two schedules, the plan
+    reports it, and dg_step with two trace arrays still equals the split
+    launches bitwise under either choice."""
+    import paper_1903_11521_amd as dg
+    _say(f"test_plan_tune N={N}")
+    plan = dg.Plan(N, 0)
+    choice = plan.tune(20_000)
+    assert isinstance(choice, bool)
+    from paper_1903_11521_amd import _lib as L
+    assert bool(L._load().dg_plan_fuses_steps(plan._h)) == choice
+    mesh, mats, Q, dt = dgtest.mesh_inputs(3, N, 12)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    args = [plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot)]
+    Qa, Qb = _dev(Q), _dev(Q)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0")
+    ta, tb = (torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0") for _ in range(2))
+    plan.step(Qa, I, ta, *args, dt, 3, traces_b=tb)
+    for _ in range(3):
+        plan.step_predict(Qb, args[0], dt, I, ta)
+        plan.step_correct(I, ta, *args, Qb)
+    assert torch.equal(Qa, Qb)
+
+
 def test_full_size_config1_sampled():
     """Degree 5 on the 40x40x40x6 = 384000-element mesh, one step in the launch
     configuration the benchmark times; 96 sampled elements re-stepped by the
