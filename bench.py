@@ -229,8 +229,8 @@ def serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                          "note (DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: the multi-GPU sharding of the step is described in the "
+                          "design notes but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
         import torch
