@@ -292,16 +292,34 @@ template <int B, typename real>
 __device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const real *acc, int64_t E)
 {
     auto blk = [&](int g) { return Q + slot_elem(L.base, g, E) * NQ * B; };
-    static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
-        constexpr int l0 = decltype(ci)::value * CH<real>;
-        constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
-        chunk_load<cnt, B>(L, [&](int g) -> const real * { return blk(g); }, l0);
+    auto cblk = [&](int g) -> const real * { return blk(g); };
+    constexpr int NCH = (B + CH<real> - 1) / CH<real>;
+    auto update = [&](auto l0c) {
+        constexpr int l0 = decltype(l0c)::value, cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
         lds_sync();
         static_for<0, cnt>([&](auto ri) { L.own[ri] += acc[l0 + ri]; });
         lds_sync();
         chunk_store<cnt, B>(L, blk, l0, E);
         lds_sync();
-    });
+    };
+    if constexpr (sizeof(real) == 4 && NCH == 2) {
+        // FP32, two chunks: both chunks' loads in flight together (one memory
+        // round trip; their registers fit beside the accumulators)
+        constexpr int c1 = B - CH<real>;
+        const auto r0 = chunk_fetch<CH<real>, B>(L, cblk, 0);
+        const auto r1 = chunk_fetch<c1, B>(L, cblk, CH<real>);
+        chunk_put<CH<real>>(L, r0);
+        update(std::integral_constant<int, 0>{});
+        chunk_put<c1>(L, r1);
+        update(std::integral_constant<int, CH<real>>{});
+    } else {
+        static_for<0, NCH>([&](auto ci) {
+            constexpr int l0 = decltype(ci)::value * CH<real>;
+            constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
+            chunk_load<cnt, B>(L, cblk, l0);
+            update(std::integral_constant<int, l0>{});
+        });
+    }
 }
 
 template <typename real>
@@ -601,10 +619,23 @@ template <int N, typename real>
 __device__ __forceinline__ void volume_acc(const Lane<real> &L, const Star<real> &S, const real *I, real *acc, int64_t E)
 {
     constexpr int B = nb3(N), Bv = nb3(N - 1);
-    star_contract<N, false, Bv>(L, S, acc, [&](auto l0c, auto cntc) {
-        constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
-        chunk_load<cnt, B>(L, [&](int g) -> const real * { return I + slot_elem(L.base, g, E) * NQ * B; }, l0);
-    });
+    auto iblk = [&](int g) -> const real * { return I + slot_elem(L.base, g, E) * NQ * B; };
+    if constexpr (sizeof(real) == 4 && (Bv + CH<real> - 1) / CH<real> == 2) {
+        // FP32, two chunks: the second chunk's loads are issued with the
+        // first, so their latency overlaps the first chunk's contraction
+        constexpr int c1 = Bv - CH<real>;
+        const auto r0 = chunk_fetch<CH<real>, B>(L, iblk, 0);
+        const auto r1 = chunk_fetch<c1, B>(L, iblk, CH<real>);
+        star_contract<N, false, Bv>(L, S, acc, [&](auto l0c, auto) {
+            if constexpr (decltype(l0c)::value == 0) chunk_put<CH<real>>(L, r0);
+            else chunk_put<c1>(L, r1);
+        });
+    } else {
+        star_contract<N, false, Bv>(L, S, acc, [&](auto l0c, auto cntc) {
+            constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
+            chunk_load<cnt, B>(L, iblk, l0);
+        });
+    }
 }
 
 template <int N, typename real>
