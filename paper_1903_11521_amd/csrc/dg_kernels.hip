@@ -302,9 +302,10 @@ __device__ __forceinline__ void add_to_q(const Lane<real> &L, real *Q, const rea
         chunk_store<cnt, B>(L, blk, l0, E);
         lds_sync();
     };
-    if constexpr (sizeof(real) == 4 && NCH == 2) {
-        // FP32, two chunks: both chunks' loads in flight together (one memory
-        // round trip; their registers fit beside the accumulators)
+    if constexpr (NCH == 2) {
+        // two chunks: both chunks' loads in flight together (one memory round
+        // trip, and no line shared by the two chunks is fetched twice; their
+        // registers fit beside the accumulators)
         constexpr int c1 = B - CH<real>;
         const auto r0 = chunk_fetch<CH<real>, B>(L, cblk, 0);
         const auto r1 = chunk_fetch<c1, B>(L, cblk, CH<real>);
@@ -620,9 +621,10 @@ __device__ __forceinline__ void volume_acc(const Lane<real> &L, const Star<real>
 {
     constexpr int B = nb3(N), Bv = nb3(N - 1);
     auto iblk = [&](int g) -> const real * { return I + slot_elem(L.base, g, E) * NQ * B; };
-    if constexpr (sizeof(real) == 4 && (Bv + CH<real> - 1) / CH<real> == 2) {
-        // FP32, two chunks: the second chunk's loads are issued with the
-        // first, so their latency overlaps the first chunk's contraction
+    if constexpr ((sizeof(real) == 4 || N <= 5) && (Bv + CH<real> - 1) / CH<real> == 2) {
+        // two chunks: the second chunk's loads are issued with the first, so
+        // their latency overlaps the first chunk's contraction (not for FP64
+        // at degree 6, whose registers are already exhausted)
         constexpr int c1 = Bv - CH<real>;
         const auto r0 = chunk_fetch<CH<real>, B>(L, iblk, 0);
         const auto r1 = chunk_fetch<c1, B>(L, iblk, CH<real>);
