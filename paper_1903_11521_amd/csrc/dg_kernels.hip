@@ -473,8 +473,11 @@ __device__ __forceinline__ void flux_lift_pair(const Lane<real> &L, const double
     }
     const real *xo = xo_buf + L.e * NQ * LB<real>;
     const real *xn = xn_buf + L.e * NQ * LB<real>;
-    static_for<0, (CNT + SB - 1) / SB>([&](auto bi) {
-        constexpr int r0 = decltype(bi)::value * SB, rn = (CNT - r0) < SB ? (CNT - r0) : SB;
+    // rows per code block: each row reads 18 LDS values, which the scheduler
+    // issues ahead for the whole block; in FP64 two rows keep that in budget
+    constexpr int SBL = sizeof(real) == 8 ? 2 : SB;
+    static_for<0, (CNT + SBL - 1) / SBL>([&](auto bi) {
+        constexpr int r0 = decltype(bi)::value * SBL, rn = (CNT - r0) < SBL ? (CNT - r0) : SBL;
         if (code_block<real>()) {
             static_for<0, rn>([&](auto rj) {
                 constexpr int r = r0 + decltype(rj)::value;
