@@ -271,6 +271,15 @@ def test_full_size_config1_sampled():
     ref = stages.step_subset(refmat.refmats(N), dt, ids, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface,
                              mesh.orient)
     assert dgtest.rel_err(Q1[ids] - Q[ids], ref - Q[ids]) <= 1e-12
+    # two steps with the benchmark's arguments (second trace array) equal two
+    # split steps bitwise at this size
+    args = (plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot))
+    Qa, Qb = _dev(Q), _dev(Q)
+    plan.step(Qa, I, tr, *args, dt, 2, traces_b=torch.empty_like(tr))
+    for _ in range(2):
+        plan.step_predict(Qb, args[0], dt, I, tr)
+        plan.step_correct(I, tr, *args, Qb)
+    assert torch.equal(Qa, Qb)
 
 
 def _mesh_tensors(dg, N, n, seed_index, prec, relabel=True):
