@@ -7,9 +7,12 @@ step is one full ADER-DG time step (predictor, time integral, volume, local
 and neighbour flux) of every element.  All inputs are resident in HBM before
 the timed region.
 
-Prints one JSON line: element-updates/s, roofline fraction of the dominant
-kernel (HIP events on the launch stream), and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+Prints one JSON line: element-updates/s; the roofline of the dominant kernel
+(HIP events on the launch stream) on the method's algorithmic bytes and
+non-zero flops, with this layout's own bytes beside them; the fraction of the
+whole step's roofline; each per-stage entry point timed with its own
+roofline fraction; and the FP64 oracle timed on the host cores (all of them
+and one) on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -25,9 +28,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
+DTYPES = {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}
 
 
 def parse():
@@ -39,6 +40,7 @@ def parse():
     ap.add_argument("--degree", type=int, default=5)
     ap.add_argument("--n", type=int, default=40, help="cubes per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", choices=["single", "batched", "serving"], default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
@@ -78,31 +80,52 @@ def measured_traffic(kernel, degree, precision):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, mesh, mats, Q, dt):
     """The FP64 oracle (plain loop nests, OpenMP over elements) on the first S
-    elements of the same workload; neighbour indices are folded into the
-    sample (same work per element)."""
+    elements of the same workload, on every host core this process may use
+    and on one core; neighbour indices are folded into the sample (same work
+    per element)."""
     from oracle import elements as oel
     from oracle import refmat, stages
     rm = refmat.refmats(args.degree)
-    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    cores = len(os.sched_getaffinity(0))
 
-    def run(S):
+    def run(S, threads):
         X = mesh.X[:S]
         star = oel.star_matrices(X, mats[:S])
         nb = (mesh.neigh[:S] % S).astype(np.int32)
         Ap, Am = oel.flux_matrices(X, mats[:S], nb)
+        stages.set_threads(threads)
         t = time.perf_counter()
         stages.step(rm, dt, Q[:S], star, Ap, Am, nb, mesh.nface[:S], mesh.orient[:S])
         return time.perf_counter() - t
 
-    S0 = 512
-    t0 = run(S0)
-    S = int(min(mesh.E, max(S0, S0 * args.cpu_seconds / max(t0, 1e-3))))
-    t = run(S)
+    def timed(threads, seconds):
+        S0 = 64 * threads
+        t0 = run(S0, threads)
+        S = int(min(mesh.E, max(S0, S0 * seconds / max(t0, 1e-3))))
+        return S, run(S, threads)
+
+    S, t = timed(cores, args.cpu_seconds)
+    S1, t1 = timed(1, args.cpu_seconds * 0.6)
+    stages.set_threads(cores)
     return {"value": S / t, "unit": "element-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": S1 / t1, "elements": S1, "seconds": t1},
             "sample": "one full time step of the first %d elements (of %d) of the same degree-%d workload, "
-                      "FP64 dense loop nests, OpenMP over elements; %.1f s" % (S, mesh.E, args.degree, t)}
+                      "FP64 dense loop nests, OpenMP over elements on %d threads (%.1f s); single thread: "
+                      "first %d elements (%.1f s)" % (S, mesh.E, args.degree, cores, t, S1, t1)}
 
 
 def batched(args):
@@ -119,8 +142,9 @@ def batched(args):
     sizes = np.exp(rng.uniform(np.log(10e3), np.log(200e3), args.meshes))
     degrees = rng.integers(2, 7, args.meshes)
     dev = torch.device("cuda:0")
+    from paper_1903_11521_amd import perfmodel as pm
+    itemsize = 8 if prec == dg.DG_FP64 else 4
     meshes, flops, nbytes = [], 0.0, 0.0
-    fms = {N: dg.flop_model(N) for N in range(2, 7)}
     for i, (Ei, N) in enumerate(zip(sizes, degrees)):
         n = max(3, int(round((Ei / 6) ** (1 / 3))))
         seed = seed_for(2) + 1000 * (i + 1)
@@ -136,9 +160,8 @@ def batched(args):
                            traces=torch.empty(plan.trace_shape(E), dtype=plan.dtype, device=dev),
                            star_packed=plan.pack_star(t(star)), Aplus=t(Ap), Aminus=t(Am),
                            neigh=t(mesh.neigh), face_rot=t(mesh.face_rot)))
-        itemsize = 8 if prec == dg.DG_FP64 else 4
-        flops += fms[int(N)]["step"] * E
-        nbytes += dg.byte_model(int(N), itemsize)["step"] * E
+        flops += pm.PAPER_NZ_PER_UPDATE[int(N)] * E
+        nbytes += pm.method_bytes(int(N), itemsize)["step"] * E
         del star, Ap, Am
     total = sum(m["E"] for m in meshes)
     log("batch of %d meshes, %d elements, degrees %s" % (len(meshes), total, sorted(set(degrees.tolist()))))
@@ -150,19 +173,14 @@ def batched(args):
     batch.step(args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ridge = 78.6e12 / 8e12
-    if flops / nbytes < ridge:
-        roof = {"bound": "hbm", "achieved": nbytes * args.steps / el / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops * args.steps / el / 1e12, "peak": 78.6, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    dtype = "f64" if prec == dg.DG_FP64 else "f32"
+    roof = pm.kernel_roofline(flops, nbytes, el / args.steps, dtype)
     roof["traffic"] = None
     roof["kernel"] = "whole batched step (all launches of one graph replay)"
     out = {"metric": "element-updates/s", "value": total * args.steps / el, "unit": "element-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
-           "data": "synthetic",
+           "dtype": DTYPES[args.precision], "data": "synthetic",
            "config": {"workload": "batched: %d independent elastic cube-split meshes, %d elements in total, "
                                   "log-uniform 10k-200k elements per mesh, degrees uniform in 2..6, one HIP graph "
                                   "replay per step" % (len(meshes), total),
@@ -217,8 +235,7 @@ def serving(args):
     out = {"metric": "element-updates/s", "value": s["element_updates_per_s"], "unit": "element-updates/s",
            "n_gpus": 1, "steps": int(steps.sum()), "warmup": 0,
            "ms_per_step": s["p50_step_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
-           "data": "synthetic",
+           "dtype": DTYPES[args.precision], "data": "synthetic",
            "config": {"workload": "serving: %d Poisson arrivals at %.1f req/s, cube-split meshes 5k-500k elements "
                                   "(log-uniform), degree 3..6, 50-500 steps each, continuous batching"
                                   % (args.requests, args.rate), "rate": args.rate},
@@ -250,6 +267,7 @@ def main():
     import torch
 
     import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
     from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
 
     N = args.degree
@@ -289,9 +307,9 @@ def main():
     elapsed = t1 - t0
     value = E * args.steps / elapsed
 
-    # per-kernel launch durations with HIP events on the launch stream
+    # per-kernel launch durations with HIP events on the launch stream (the
+    # timed region is one predictor, steps-1 fused-step calls, one corrector)
     log("per-kernel event timing")
-    # (the timed region is one predictor, steps-1 fused launches, one corrector)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for k in range(args.steps):
         ev[k][0].record(stream)
@@ -302,53 +320,96 @@ def main():
         plan.step_correct(I, tr2, star_p, Apg, Amg, neigh, face_rot, Qg)
         ev[k][3].record(stream)
     torch.cuda.synchronize()
-    mean_ms = lambda a, b: float(np.mean([ev[k][a].elapsed_time(ev[k][b]) for k in range(args.steps)])) * 1e-3
-    t_pred, t_fused, t_corr = mean_ms(0, 1), mean_ms(1, 2), mean_ms(2, 3)
+    mean_s = lambda a, b: float(np.mean([ev[k][a].elapsed_time(ev[k][b]) for k in range(args.steps)])) * 1e-3
+    t_pred, t_fused, t_corr = mean_s(0, 1), mean_s(1, 2), mean_s(2, 3)
     itemsize = 8 if prec == dg.DG_FP64 else 4
+    dtype = "f64" if prec == dg.DG_FP64 else "f32"
     counts = np.bincount(mesh.orient.ravel(), minlength=3) / mesh.orient.size
-    fm = dg.flop_model(N, counts)
-    bm = dg.byte_model(N, itemsize)
+    sf = pm.stage_flops(N, counts)
+    mb = pm.method_bytes(N, itemsize)
+    lb = pm.layout_bytes(N, itemsize)
+    # the dominant kernel: the fused launch where the plan fuses, else the
+    # slower of corrector and predictor
     if plan.fuses_steps and args.steps > 1:
         kern, tk = "step_fused", t_fused
+        kflops, kbytes, klayout = sf["step"], mb["step"], lb["step_fused"]
     else:
         kern, tk = max((("step_correct", t_corr), ("step_predict", t_pred)), key=lambda kt: kt[1])
-    flops, nbytes = fm[kern] * E, bm[kern] * E
-    peak_flops = PEAK_FP64_TFLOPS if prec == dg.DG_FP64 else 78.6   # VALU FMA (no packed FP32)
-    ridge = peak_flops * 1e12 / (PEAK_HBM_GBS * 1e9)
-    if flops / nbytes < ridge:
-        roof = {"bound": "hbm", "achieved": nbytes / tk / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops / tk / 1e12, "peak": peak_flops, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+        kflops, kbytes, klayout = sf[kern], mb[kern], lb[kern]
+    roof = pm.kernel_roofline(kflops * E, kbytes * E, tk, dtype)
     roof["traffic"] = measured_traffic(kern, N, args.precision)
     roof["kernel"] = kern
     roof["kernel_ms"] = tk * 1e3
-    roof["algorithmic_bytes_per_launch"] = nbytes
-    roof["algorithmic_flops_per_launch"] = flops
-    step_flops = fm["step"] * E
+    roof["algorithmic_bytes_per_launch"] = kbytes * E
+    roof["algorithmic_bytes_per_element"] = kbytes
+    roof["algorithmic_flops_per_launch"] = kflops * E
+    roof["layout_bytes_per_launch"] = klayout * E
+    roof["layout_hbm_gbs"] = klayout * E / tk / 1e9
+    step_rate = pm.step_roofline_rate(N, itemsize, dtype)
     out = {
         "metric": "element-updates/s", "value": value, "unit": "element-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}[args.precision],
-        "data": "synthetic",
+        "dtype": DTYPES[args.precision], "data": "synthetic",
         "config": {"workload": "elastic ADER-DG, degree %d (B=%d), %dx%dx%dx6 = %d-element jittered periodic "
                                "cube-split mesh, random materials, %d time steps, %s" % (
                                    N, plan.B, args.n, args.n, args.n, E, args.steps,
                                    "one launch per step (corrector fused with the next predictor)"
                                    if plan.fuses_steps else "predictor and corrector launch per step"),
                    "elements": E, "degree": N, "dt": dt},
-        "useful_gflops": step_flops * args.steps / elapsed / 1e9,
+        "useful_gflops": pm.PAPER_NZ_PER_UPDATE[N] * value / 1e9,
         "kernel_ms": dict({"step_predict": t_pred * 1e3, "step_correct": t_corr * 1e3},
                           **({"step_fused": t_fused * 1e3} if plan.fuses_steps else {})),
         "roofline": roof,
+        "step_roofline": {"element_updates_per_s": step_rate, "frac": value / step_rate,
+                          "flops_per_update": pm.PAPER_NZ_PER_UPDATE[N], "bytes_per_update": mb["step"],
+                          "bound": pm.roofline(pm.PAPER_NZ_PER_UPDATE[N], mb["step"], dtype)["bound"]},
         "paper_context": "paper's best single-simulation O6 DP CPU figure: 1244 MDoF/s on 2x Xeon 8174 "
-                         "(about 2.47 M element-updates/s); context, not the target",
+                         "(about 2.47 M element-updates/s, 15.3 % of NZ peak); context, not the target",
     }
+    if not args.no_stages:
+        log("per-stage timing")
+        out["stages"] = time_stages(plan, E, Qg, star_p, Apg, Amg, neigh, face_rot, dt, sf, mb, dtype, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args, mesh, mats, Q, dt)
     print(json.dumps(out), flush=True)
+
+
+def time_stages(plan, E, Q, star_p, Ap, Am, neigh, face_rot, dt, sf, mb, dtype, stream, reps=5):
+    """Each per-stage entry point (dg_predictor ... dg_neighbour_flux) on the
+    same workload, HIP events on the launch stream, mean over `reps` calls
+    after one warm-up; per stage its roofline fraction on the method bytes,
+    and the element-updates/s of the step done stage by stage."""
+    import torch
+    from paper_1903_11521_amd import perfmodel as pm
+    T = torch.empty(plan.deriv_shape(E), dtype=plan.dtype, device=Q.device)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device=Q.device)
+    Qs = Q.clone()
+    calls = {
+        "predictor": lambda: plan.predictor(Qs, star_p, dt, T),
+        "time_integral": lambda: plan.time_integral(T, dt, I),
+        "volume": lambda: plan.volume(I, star_p, Qs),
+        "local_flux": lambda: plan.local_flux(I, Ap, Qs),
+        "neighbour_flux": lambda: plan.neighbour_flux(I, neigh, face_rot, Am, Qs),
+    }
+    out, total = {}, 0.0
+    for name, fn in calls.items():
+        fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+        total += t
+        r = pm.kernel_roofline(sf[name] * E, mb[name] * E, t, dtype)
+        out[name] = {"ms": t * 1e3, "bound": r["bound"], "achieved": r["achieved"], "unit": r["unit"],
+                     "frac": r["frac"], "bytes_per_element": mb[name], "flops_per_element": sf[name]}
+    out["per_stage_step_element_updates_per_s"] = E / total
+    del T, I, Qs
+    return out
 
 
 if __name__ == "__main__":

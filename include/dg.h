@@ -59,8 +59,8 @@
  * reported synchronously and nothing is enqueued.  A failed kernel launch
  * returns DG_EHIP; faults during execution surface from dg_sync.  The text
  * of the last error of the calling thread is available from dg_last_error.
- * Plans are immutable after creation (except for dg_plan_tune) and may be
- * shared between threads.
+ * Plans are immutable after creation (except for dg_plan_tune and
+ * dg_plan_set_fusion) and may be shared between threads.
  */
 #ifndef DG_H
 #define DG_H
@@ -127,9 +127,27 @@ int dg_plan_fuses_steps(const dg_plan *plan);
  * 1 (fused) or 0 (two launches), or a negative status.  Allocates and frees
  * its own device work buffers (about E times the per-element footprint) and
  * synchronises the stream.  Call it before the plan is shared between
- * threads; it is the only call that changes a plan.  E in [64, 2^26]. */
+ * threads (it and dg_plan_set_fusion are the only calls that change a
+ * plan).  E in [64, 2^26]. */
 int dg_plan_tune(dg_plan *plan, int64_t E, hipStream_t stream);
+/* Sets the launch schedule of dg_step (with a second trace array) and
+ * dg_step_fused: fused = 1 runs step k's corrector and step k+1's predictor as
+ * one launch, fused = 0 as two launches.  Both give the same result bit for
+ * bit; the choice only changes speed.  Like dg_plan_tune it changes the plan:
+ * call it before the plan is shared between threads.  DG_EINVAL if fused is
+ * neither 0 nor 1. */
+int dg_plan_set_fusion(dg_plan *plan, int fused);
 const char *dg_last_error(void);
+
+/* Debug checks (process wide, off by default; returns the previous setting).
+ * When on, every call that takes a neighbour table (dg_neighbour_flux,
+ * dg_step, dg_step_correct, dg_step_fused, dg_batch_create) first waits for
+ * the work already queued on its stream, copies the table to the host and
+ * returns DG_EINVAL, with the offending element and face in dg_last_error and
+ * nothing enqueued, if an entry lies outside [-1, bound) (bound = n_I for
+ * dg_neighbour_flux, E otherwise).  With the checks off such entries are
+ * treated like -1 (no neighbour) and are not reported. */
+int dg_set_debug_checks(int enable);
 
 /* ---- device compute calls (stream ordered) ----------------------------- */
 
@@ -173,7 +191,9 @@ int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I
  * predictor run as one launch (one launch per step; the traces alternate
  * between the two arrays, because neighbours still read step k's traces
  * while step k+1's are written).  Otherwise each step is two launches.  All
- * give the same result bit for bit.  Neighbour indices must lie in [0, E); others are treated like -1. */
+ * give the same result bit for bit.  Neighbour indices must lie in [0, E)
+ * or be -1; others are treated like -1, or rejected with DG_EINVAL when the
+ * debug checks are on (dg_set_debug_checks). */
 int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
             void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
             const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);

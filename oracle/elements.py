@@ -134,7 +134,9 @@ def godunov_face_matrices(matL, matR):
 def flux_matrices(X, materials, neigh, neighbour_materials=None):
     """(Aplus, Aminus), each (E, 4, 9, 9), in the form used by the update:
     Q += sum_s Rhat^s (R^s^T I) Aplus^s^T + neighbour analogue with Aminus.
-    neighbour_materials (E, 4, 3), if given, replaces materials[neigh]."""
+    neighbour_materials (E, 4, 3), if given, replaces materials[neigh].
+    Faces with neigh < 0 (no neighbour): A+ uses the element's own material
+    on both sides and A- is zero."""
     E = X.shape[0]
     _, det, _ = geometry(X)
     n, s, t, area = face_frames(X)
@@ -142,9 +144,18 @@ def flux_matrices(X, materials, neigh, neighbour_materials=None):
     T = rotation_9x9(Qm)
     Tinv = rotation_9x9(np.swapaxes(Qm, -1, -2))
     matL = np.broadcast_to(materials[:, None, :], (E, 4, 3))
-    matR = materials[neigh] if neighbour_materials is None else neighbour_materials
+    if neighbour_materials is None:
+        # a face without neighbour (neigh < 0) takes the element's own
+        # material on the far side: A+ is then the upwind flux of a
+        # homogeneous medium, and A- is zero (no neighbour term)
+        nb = np.asarray(neigh)
+        matR = np.where((nb >= 0)[..., None], materials[np.where(nb >= 0, nb, 0)], matL)
+    else:
+        matR = neighbour_materials
     Ap, Am = godunov_face_matrices(matL, matR)
     scale = -(2.0 * area / det[:, None])[..., None, None]
     Aplus = scale * (T @ Ap @ Tinv)
     Aminus = scale * (T @ Am @ Tinv)
+    if neighbour_materials is None:
+        Aminus[np.asarray(neigh) < 0] = 0.0
     return Aplus, Aminus

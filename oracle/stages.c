@@ -13,11 +13,16 @@
  *   DOFs: Q, I, dQ [E][P][B]  (basis index fastest);  D [E][N+1][P][B]
  *   neighbours: neigh [E][4] (int32, -1 = none), nface, orient [E][4] (int8)
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define IDX3(a, b, c, nb, nc) (((size_t)(a) * (nb) + (b)) * (nc) + (c))
+
+/* Number of OpenMP threads of the loops below (timing runs only). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* Eq. seissol:derivative:  D^{d+1}_kp = sum_xi Kt^xi_kl D^d_lq Astar^xi_pq,
  * evaluated as  tmp_lp = D_lq Astar_pq  then  D'_kp += Kt_kl tmp_lp.      */

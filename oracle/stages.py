@@ -53,8 +53,19 @@ def _load():
             lib.oracle_volume.argtypes = [I, I, L, dp, dp, dp, dp]
             lib.oracle_local_flux.argtypes = [I, I, I, L, dp, dp, dp, dp, dp]
             lib.oracle_neighbour_flux.argtypes = [I, I, I, L, dp, dp, dp, i32p, i8p, i8p, dp, dp, dp]
+            lib.oracle_set_threads.argtypes = [I]
+            lib.oracle_max_threads.restype = I
             _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP thread count of the loop nests (for timing runs)."""
+    _load().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
 
 
 def _p(a, ctype=ctypes.c_double):

@@ -6,8 +6,9 @@ marshalling only: every stage of the scheme runs in the HIP library
 provides device memory and the current stream.  There is no CPU fallback: if
 the library is missing, every call raises.
 """
-from ._lib import (DG_FP32, DG_FP64, DG_MIXED, Batch, DGError, Plan, byte_model, element_data,
-                   flop_model, library_path, reference_matrices)
+from . import perfmodel
+from ._lib import (DG_FP32, DG_FP64, DG_MIXED, Batch, DGError, Plan, element_data, flop_model, library_path,
+                   reference_matrices, set_debug_checks)
 
 __all__ = ["Plan", "Batch", "DGError", "DG_FP64", "DG_FP32", "DG_MIXED", "reference_matrices",
-           "element_data", "library_path", "flop_model", "byte_model"]
+           "element_data", "library_path", "flop_model", "perfmodel", "set_debug_checks"]

@@ -64,6 +64,8 @@ def _load():
         lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_plan_fuses_steps.argtypes = [vp]
         lib.dg_plan_tune.argtypes = [vp, i64, vp]
+        lib.dg_plan_set_fusion.argtypes = [vp, i32]
+        lib.dg_set_debug_checks.argtypes = [i32]
         lib.dg_step_predict.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp]
         lib.dg_step_correct.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_sync.argtypes = [vp]
@@ -77,6 +79,12 @@ def _load():
 def _check(rc):
     if rc != 0:
         raise DGError("dg error %d: %s" % (rc, _load().dg_last_error().decode(errors="replace")))
+
+
+def set_debug_checks(enable: bool) -> bool:
+    """Process-wide synchronous validation of neighbour tables (see
+    dg_set_debug_checks in include/dg.h); returns the previous setting."""
+    return bool(_load().dg_set_debug_checks(1 if enable else 0))
 
 
 def _dptr(a):
@@ -154,23 +162,6 @@ def flop_model(degree: int, orient_counts=None) -> dict:
                 B=B, Bf=Bf)
 
 
-def byte_model(degree: int, itemsize: int = 8) -> dict:
-    """Algorithmic HBM bytes per element of the step kernels: every array read
-    or written once (neighbour traces with ideal reuse); A+/A- FP64.
-    step_fused is the corrector of one step with the predictor of the next."""
-    N = degree
-    B, Bf = comb(N + 3, 3), comb(N + 2, 2)
-    q = 9 * B * itemsize
-    tr = 4 * 9 * Bf * itemsize
-    star = 81 * itemsize
-    flux = 2 * 4 * 81 * 8
-    tables = 4 * 4 + 4
-    predict = q + star + q + tr                      # Q, star -> I, traces
-    correct = q + tr + tr + star + flux + tables + q + q   # I, own+nbr traces, star, A+-, tables, Q rw
-    fused = correct + q + tr                         # + next I and traces (Q, star read once)
-    return dict(step_predict=predict, step_correct=correct, step=predict + correct, step_fused=fused)
-
-
 # ---------------------------------------------------------------------------
 # device plans (torch tensors for memory and streams)
 # ---------------------------------------------------------------------------
@@ -203,6 +194,12 @@ class Plan:
         _check(r if r < 0 else 0)
         self.fuses_steps = bool(r)
         return self.fuses_steps
+
+    def set_fusion(self, fused: bool):
+        """Force the step schedule: True = corrector of step k and predictor
+        of step k+1 in one launch, False = two launches (same result)."""
+        _check(_load().dg_plan_set_fusion(self._h, 1 if fused else 0))
+        self.fuses_steps = bool(fused)
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -7,6 +7,7 @@ into paper_1903_11521_amd/libdg_mi355x.so.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import re
 import subprocess
@@ -50,7 +51,33 @@ def kernel_usage(text):
     return usage
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def _stamp(cmd, inputs):
+    """Hash of a compile command and the contents of its inputs."""
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for f in inputs:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _compile(cmd, inputs, incremental):
+    """Run one compile step; with `incremental`, skip it when the object's
+    stamp matches (its remarks are then read back from the stamp file)."""
+    out = cmd[cmd.index("-o") + 1]
+    st = out + ".stamp"
+    key = _stamp(cmd, inputs)
+    if incremental and os.path.exists(out) and os.path.exists(st):
+        with open(st) as fh:
+            old = fh.read()
+        if old.startswith(key + "\n"):
+            return old[len(key) + 1:]
+    text = _run(cmd)
+    with open(st, "w") as fh:
+        fh.write(key + "\n" + text)
+    return text
+
+
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
     os.makedirs(GEN, exist_ok=True)
     host = os.path.join(BUILD, "librefmat_host.so")
     _run(["g++", "-O2", "-shared", "-fPIC", "-DDG_REFMAT_STANDALONE", os.path.join(CSRC, "refmat.cpp"),
@@ -61,8 +88,18 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     finally:
         sys.path.pop(0)
     codegen.generate(host, os.path.join(GEN, "dg_generated.h"))
+    sys.path.insert(0, PKG)
+    try:
+        import codegen_mfma  # noqa: E402
+    finally:
+        sys.path.pop(0)
+    codegen_mfma.generate(host, os.path.join(GEN, "mfma_tables.h"))
     objs = []
     cmds = []
+    headers = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".h", ".inc", ".hip"))]
+    headers += [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))]
+    headers.append(os.path.join(GEN, "dg_generated.h"))
+    headers.append(os.path.join(GEN, "mfma_tables.h"))
     for n in DEGREES:
         o = os.path.join(BUILD, "dg_launch_%d.o" % n)
         cmds.append([HIPCC] + HIP_FLAGS + ["-DDG_DEGREE=%d" % n, "-Rpass-analysis=kernel-resource-usage",
@@ -74,7 +111,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         objs.append(o)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:
-        outs = list(ex.map(_run, cmds))
+        outs = list(ex.map(lambda c: _compile(c, [c[c.index("-c") + 1]] + headers, incremental), cmds))
     usage = kernel_usage("\n".join(outs))
     spills = {k: v for k, v in usage.items() if v.get("ScratchSize", 0) > 0}
     if spills:
@@ -93,4 +130,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -116,15 +116,9 @@ def check_structure(N, M):
 def gen_degree(em, N, M):
     check_structure(N, M)
     B, Bf = M["B"], M["Bf"]
-    consts = {}
-
-    def add(name, vals):
-        consts[name] = vals
-
     # K-tilde, column(L)-major, then d, then k
     for key, nm in (("Kt", "KtCol"), ("Kh", "KhCol")):
         A = M[key]
-        vals = []
         bodies = []
         for L in range(B):
             stm = []
@@ -133,10 +127,7 @@ def gen_degree(em, N, M):
                     v = A[d, k, L]
                     if v != 0.0:
                         stm.append(f"acc[{k}] = fma({_lit(v)}, x{d}, acc[{k}]);")
-                        vals.append(v)
             bodies.append(stm)
-        cname = f"g_{key}{N}"
-        add(cname, vals)
         for L in range(B):
             em(f"template <> struct {nm}<{N}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real x0, real x1, real x2, real* __restrict__ acc) {{")
             for s in fenced(bodies[L]):
@@ -144,37 +135,30 @@ def gen_degree(em, N, M):
             em("} };")
     # R: trace, row(L)-major per face S, then m
     for S in range(4):
-        vals = []
         for L in range(B):
             stm = []
             for m in range(Bf):
                 v = M["R"][S, L, m]
                 if v != 0.0:
                     stm.append(f"tr[{m}] = fma({_lit(v)}, v, tr[{m}]);")
-                    vals.append(v)
             em(f"template <> struct RCol<{N}, {S}, {L}> {{ template <typename real> __device__ __forceinline__ static void apply(real v, real* __restrict__ tr) {{")
             for s in fenced(stm):
                 em("  " + s)
             em("} };")
-        add(f"g_R{N}_{S}", vals)
     # R-hat: lift, column(M)-major per face, then k
     for S in range(4):
-        vals = []
         for Mi in range(Bf):
             stm = []
             for k in range(B):
                 v = M["Rh"][S, k, Mi]
                 if v != 0.0:
                     stm.append(f"acc[{k}] = fma({_lit(v)}, g, acc[{k}]);")
-                    vals.append(v)
             em(f"template <> struct RhCol<{N}, {S}, {Mi}> {{ template <typename real> __device__ __forceinline__ static void apply(real g, real* __restrict__ acc) {{")
             for s in fenced(stm):
                 em("  " + s)
             em("} };")
-        add(f"g_Rh{N}_{S}", vals)
     # f^h: full apply
     for H in range(3):
-        vals = []
         em(f"template <> struct FApply<{N}, {H}> {{ template <typename real> __device__ __forceinline__ static void apply(const real* __restrict__ in, real* __restrict__ out) {{")
         for m in range(Bf):
             terms = [(n, M["f"][H, m, n]) for n in range(Bf) if M["f"][H, m, n] != 0.0]
@@ -183,12 +167,9 @@ def gen_degree(em, N, M):
                 continue
             n0, v0 = terms[0]
             em(f"  out[{m}] = {_lit(v0)} * in[{n0}];")
-            vals.append(v0)
             for n, v in terms[1:]:
                 em(f"  out[{m}] = fma({_lit(v)}, in[{n}], out[{m}]);")
-                vals.append(v)
         em("} };")
-        add(f"g_F{N}_{H}", vals)
     # f^h one degree block at a time (f^h is block diagonal by degree: the
     # orientation maps are measure-preserving affine symmetries of the
     # reference triangle, which keep each degree's orthogonal subspace)
@@ -206,7 +187,6 @@ def gen_degree(em, N, M):
                 for j, v in terms[1:]:
                     em(f"  out[{i}] = fma({_lit(v)}, in[{j}], out[{i}]);")
             em("} };")
-    return consts
 
 
 def flop_counts(M, N):
@@ -232,18 +212,13 @@ def generate(host_lib_path, out_path):
     em("template <int N, int S, int M> struct RhCol;")
     em("template <int N, int H> struct FApply;")
     em("template <int N, int H, int D> struct FBlock;")
-    allc = {}
     stats = {}
     for N in DEGREES:
         M = matrices(lib, N)
-        allc.update(gen_degree(em, N, M))
+        gen_degree(em, N, M)
         stats[N] = flop_counts(M, N)
-    body = em.lines
-    em2 = Emitter()
-    em2.lines = body[:8]
-    em2.lines += body[8:]
     with open(out_path + ".tmp", "w") as fh:
-        fh.write("\n".join(em2.lines) + "\n")
+        fh.write("\n".join(em.lines) + "\n")
     os.replace(out_path + ".tmp", out_path)
     return stats
 

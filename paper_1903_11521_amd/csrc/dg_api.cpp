@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <utility>
@@ -43,6 +44,37 @@ int hip_status(hipError_t e, const char *where)
     g_err = buf;
     return DG_EHIP;
 }
+
+// Synchronous validation of neighbour tables (off by default; see
+// dg_set_debug_checks).  Copies the table to the host after the work already
+// queued on the stream and checks every entry.
+std::atomic<int> g_debug_checks{0};
+
+int check_neighbours(const int32_t *neigh, int64_t E, int64_t bound, hipStream_t s, const char *who)
+{
+    if (!g_debug_checks.load() || E == 0) return DG_OK;
+    std::vector<int32_t> h((size_t)E * 4);
+    hipError_t e = hipMemcpyAsync(h.data(), neigh, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, who);
+    for (int64_t i = 0; i < E * 4; ++i) {
+        const int32_t v = h[(size_t)i];
+        if (v < -1 || v >= bound) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "%s: neighbour index %d of element %lld face %d outside [-1, %lld)", who,
+                          (int)v, (long long)(i / 4), (int)(i % 4), (long long)bound);
+            g_err = buf;
+            return DG_EINVAL;
+        }
+    }
+    return DG_OK;
+}
+
+#define CHECK_NEIGH(neigh, E, bound, s, who)                                        \
+    do {                                                                            \
+        const int rc_ = check_neighbours((neigh), (E), (bound), (s), (who));       \
+        if (rc_ != DG_OK) return rc_;                                               \
+    } while (0)
 
 struct Tables {
     DgTable t[3][7];   // [precision][degree]
@@ -210,6 +242,7 @@ int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I
     CHECK_PTR(E, face_rot, "face_rot");
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, Q, "Q");
+    CHECK_NEIGH(neigh, E, n_I, s, "dg_neighbour_flux");
     return hip_status(plan->tab.neighbour_flux(E, n_I, I, neigh, face_rot, Aminus, Q, s), "dg_neighbour_flux");
 }
 
@@ -231,6 +264,7 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
+    CHECK_NEIGH(neigh, E, E, s, "dg_step");
     if (!traces_b || n_steps < 2 || !plan->tab.fuse_step) {
         const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
         for (int n = 0; n < n_steps; ++n) {
@@ -288,6 +322,7 @@ int dg_step_correct(const dg_plan *plan, int64_t E, const void *I, const void *t
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
     CHECK_PTR(E, Q, "Q");
+    CHECK_NEIGH(neigh, E, E, s, "dg_step_correct");
     const DgItem it = make_item(E, 0.0, Q, const_cast<void *>(I), const_cast<void *>(traces), star_packed, Aplus,
                                 Aminus, neigh, face_rot);
     return hip_status(plan->tab.step_correct(it, s), "dg_step_correct");
@@ -309,6 +344,7 @@ int dg_step_fused(const dg_plan *plan, int64_t E, double dt, void *Q, void *I, c
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
+    CHECK_NEIGH(neigh, E, E, s, "dg_step_fused");
     DgItem it = make_item(E, dt, Q, I, const_cast<void *>(traces_in), star_packed, Aplus, Aminus, neigh, face_rot);
     if (plan->tab.fuse_step) return hip_status(plan->tab.step_fused(it, traces_out, s), "dg_step_fused");
     // same work as two launches
@@ -322,6 +358,19 @@ int dg_plan_fuses_steps(const dg_plan *plan)
 {
     CHECK_PLAN(plan);
     return plan->tab.fuse_step ? 1 : 0;
+}
+
+int dg_plan_set_fusion(dg_plan *plan, int fused)
+{
+    CHECK_PLAN(plan);
+    if (fused != 0 && fused != 1) return fail(DG_EINVAL, "fusion mode %s%lld is neither 0 nor 1", "", fused);
+    plan->tab.fuse_step = fused == 1;
+    return DG_OK;
+}
+
+int dg_set_debug_checks(int enable)
+{
+    return g_debug_checks.exchange(enable ? 1 : 0);
 }
 
 namespace {
@@ -456,6 +505,7 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
         CHECK_PTR(x.E, x.Aminus, "item Aminus");
         CHECK_PTR(x.E, x.neigh, "item neigh");
         CHECK_PTR(x.E, x.face_rot, "item face_rot");
+        CHECK_NEIGH(x.neigh, x.E, x.E, nullptr, "dg_batch_create");
     }
     std::unique_ptr<dg_batch> b(new (std::nothrow) dg_batch);
     if (!b) return fail(DG_ENOMEM, "out of host memory%s", "");

@@ -180,6 +180,7 @@ class GpuExecutor:
         self.stream = torch.cuda.current_stream()
         self.pool = ThreadPoolExecutor(host_workers)
         self.futures = {}
+        self.history = []            # the request sets of successive batches
 
     def prepare(self, req: Request):
         """Start the host-side setup (mesh tables, element data) in a worker
@@ -205,6 +206,7 @@ class GpuExecutor:
             neigh=t(h["neigh"]), face_rot=t(h["face_rot"]))
 
     def rebuild(self, rids):
+        self.history.append(sorted(rids))
         if self.batch is not None:
             self.torch.cuda.synchronize()        # the old graph may still be running
             self.batch.close()

@@ -97,14 +97,25 @@ def test_plan_argument_errors():
 
 def test_flop_and_byte_models():
     import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
     _lib()
     f = dg.flop_model(5)
     # the paper's SeisSol kernels at order 6 need about 253.5k non-zero flops per
     # element-update (appendix tables); this algorithm computes the face traces
     # once per element, so it needs somewhat fewer
     assert 150e3 < f["step"] < 300e3
-    b = dg.byte_model(5)
-    assert b["step"] > 30e3
-    # the fused launch saves the predictor's reads of Q and star
-    assert b["step_fused"] == b["step"] - 9 * 56 * 8 - 81 * 8
-    assert f["step_fused"] == f["step"]
+    # method bytes per element at degree 5, FP64: Q 4032 B, packed star 648 B,
+    # A+ and A- 2592 B each, tables 20 B
+    b = pm.method_bytes(5)
+    assert b["step_correct"] == 4032 * 3 + 648 + 2 * 2592 + 20
+    assert b["step_predict"] == 4032 * 2 + 648
+    assert b["step"] == 4032 * 4 + 648 + 2 * 2592 + 20
+    assert b["predictor"] == 4032 + 648 + 72 * (56 + 35 + 20 + 10 + 4 + 1)
+    # the layout's own bytes add the face traces (6048 B per element)
+    lb = pm.layout_bytes(5)
+    assert lb["step_correct"] - b["step_correct"] == 2 * 6048
+    # step rooflines: 310 M/s at degree 5 and 155 M/s at degree 6 (FP64)
+    assert abs(pm.step_roofline_rate(5) / 310.06e6 - 1) < 1e-3
+    assert abs(pm.step_roofline_rate(6) / 155.34e6 - 1) < 1e-3
+    r = pm.kernel_roofline(135e3 * 1000, 17948 * 1000, 17948 * 1000 / 4e12)
+    assert r["bound"] == "hbm" and abs(r["frac"] - 0.5) < 1e-12

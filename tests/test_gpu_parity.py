@@ -1,6 +1,12 @@
 """GPU parity: every stage and the full step through the C ABI against the
-FP64 oracle on the same seeded inputs.  FP64 bar 1e-12, FP32 bar 1e-5
-(relative Frobenius error per quantity, increments for update stages)."""
+FP64 oracle on the same seeded inputs.
+
+Bars (both the per-quantity Frobenius metric and the per-element metric of
+dgtest must pass): FP64 1e-12, FP32 and mixed 1e-5, for every stage (each
+derivative order of the predictor, the time integral, the volume, local and
+neighbour flux increments), for Q after one or more full steps, and for the
+full-step increment Q^{n+1} - Q^n (relative to the increment).
+"""
 import math
 import sys
 
@@ -8,12 +14,14 @@ import numpy as np
 import pytest
 
 import dgtest
+from dgtest import assert_close
 from oracle import refmat, stages
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 1e-5, 2: 1e-5}
+TOL_INC = TOL                               # full-step increments: the same bars
 
 
 def _dev(a, dtype=None):
@@ -38,6 +46,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
+def _rounded(Q, prec):
+    """The initial DOFs as the GPU holds them (FP32 plans round once)."""
+    return Q.astype(np.float32).astype(np.float64) if prec else Q
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("N,E", [(2, 30), (3, 52), (4, 17), (5, 52), (6, 23)])
 def test_stages(N, E, prec):
@@ -49,32 +62,31 @@ def test_stages(N, E, prec):
     tol = TOL[prec]
     fdt = plan.dtype
     star_p = plan.pack_star(_dev(d["star"]))
-    # predictor (Taylor-scaled derivatives)
+    # predictor (Taylor-scaled derivatives), every order at the stage bar
     T = plan.predictor(_dev(d["Q"], fdt), star_p, dt)
     D = stages.predictor(rm, d["star"], d["Q"])
     scale = np.array([dt ** k / math.factorial(k) for k in range(N + 1)])
     Tref = D * scale[None, :, None, None]
     Tg = _host(T)
     for k in range(N + 1):
-        assert dgtest.rel_err(Tg[:, k], Tref[:, k]) <= tol * (4 if k > 2 else 1), f"derivative {k}"
+        assert_close(Tg[:, k], Tref[:, k], tol, f"derivative {k}")
     # time integral from the oracle's derivatives
     I = plan.time_integral(_dev(Tref, fdt), dt)
-    assert dgtest.rel_err(_host(I), stages.time_integral(N, D, dt)) <= tol
+    assert_close(_host(I), stages.time_integral(N, D, dt), tol, "time integral")
     # update stages as increments on Q = 0
     Iin = _dev(d["I"], fdt)
     zero = lambda: torch.zeros(plan.dof_shape(E), dtype=fdt, device="cuda:0")
     q = plan.volume(Iin, star_p, zero())
-    assert dgtest.rel_err(_host(q), stages.volume(rm, d["star"], d["I"])) <= tol
+    assert_close(_host(q), stages.volume(rm, d["star"], d["I"]), tol, "volume")
     q = plan.local_flux(Iin, _dev(d["Ap"]), zero())
-    assert dgtest.rel_err(_host(q), stages.local_flux(rm, d["Ap"], d["I"])) <= tol
+    assert_close(_host(q), stages.local_flux(rm, d["Ap"], d["I"]), tol, "local flux")
     q = plan.neighbour_flux(Iin, _dev(d["neigh"]), _dev(d["face_rot"]), _dev(d["Am"]), zero())
     ref = stages.neighbour_flux(rm, d["Am"], d["I"], d["neigh"], d["nface"], d["orient"])
-    assert dgtest.rel_err(_host(q), ref) <= tol
-    # add-to-Q path with a non-zero Q
+    assert_close(_host(q), ref, tol, "neighbour flux")
+    # add-to-Q path with a non-zero Q: Q + volume, compared as Q^{n+1}
     Q0 = _dev(d["Q"], fdt)
     plan.volume(Iin, star_p, Q0)
-    inc = _host(Q0) - d["Q"].astype(np.float32 if prec else np.float64).astype(np.float64)
-    assert dgtest.rel_err(inc, stages.volume(rm, d["star"], d["I"])) <= tol * 10
+    assert_close(_host(Q0), _rounded(d["Q"], prec) + stages.volume(rm, d["star"], d["I"]), tol, "Q + volume")
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -97,9 +109,8 @@ def test_step_config0(prec):
     plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
               _dev(mesh.face_rot), dt, 1)
     Q1 = _host(Qg)
-    Qin = Q.astype(np.float32).astype(np.float64) if prec else Q
-    assert dgtest.rel_err(Q1 - Qin, ref - Q) <= TOL[prec] * (10 if prec else 1)
-    assert dgtest.rel_err(Q1, ref) <= TOL[prec]
+    assert_close(Q1 - _rounded(Q, prec), ref - Q, TOL_INC[prec], "step increment")
+    assert_close(Q1, ref, TOL[prec], "Q^{n+1}")
 
 
 @pytest.mark.parametrize("fused", [False, True])
@@ -116,6 +127,8 @@ def test_step_multi_relabelled_degree5(fused):
     for _ in range(3):
         ref = stages.step(rm, dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
     plan = dg.Plan(N, 0)
+    if fused:
+        plan.set_fusion(True)
     star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
     E = mesh.E
     Qg = _dev(Q)
@@ -123,7 +136,7 @@ def test_step_multi_relabelled_degree5(fused):
     tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0")
     plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
               _dev(mesh.face_rot), dt, 3, traces_b=torch.empty_like(tr) if fused else None)
-    assert dgtest.rel_err(_host(Qg) - Q, ref - Q) <= 1e-12
+    assert_close(_host(Qg) - Q, ref - Q, 1e-12, "3-step increment")
 
 
 @pytest.mark.parametrize("E", [0, 1, 7, 8])
@@ -154,13 +167,13 @@ def test_edge_sizes(E):
     tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
     args = (plan.pack_star(_dev(d["star"])), _dev(d["Ap"]), _dev(d["Am"]), _dev(neigh), _dev(d["face_rot"]))
     plan.step(Qg, I, tr, *args, 0.05, 1)
-    assert dgtest.rel_err(_host(Qg) - d["Q"], ref - d["Q"]) <= 1e-12
+    assert_close(_host(Qg) - d["Q"], ref - d["Q"], 1e-12, "step increment")
     # two more steps, fused, against the oracle
     ref2 = ref
     for _ in range(2):
         ref2 = stages.step(rm, 0.05, ref2, d["star"], d["Ap"], d["Am"], neigh, d["nface"], d["orient"])
     plan.step(Qg, I, tr, *args, 0.05, 2, traces_b=torch.empty_like(tr))
-    assert dgtest.rel_err(_host(Qg) - ref, ref2 - ref) <= 1e-12
+    assert_close(_host(Qg) - ref, ref2 - ref, 1e-12, "fused 2-step increment")
 
 
 def test_step_split_equals_step():
@@ -182,16 +195,24 @@ def test_step_split_equals_step():
     assert torch.equal(Qa, Qb)
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-@pytest.mark.parametrize("N", [2, 3, 5, 6])
-def test_fused_step_equals_split(N, prec):
-    """dg_step with a second trace array (corrector and next predictor in one
-    launch) is bitwise the sequence of dg_step_predict + dg_step_correct, for
-    Q and for the last step's traces, with odd and even step counts."""
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_fused_step_equals_split(N, prec, fused):
+    """dg_step with a second trace array is bitwise the sequence of
+    dg_step_predict + dg_step_correct, for Q, I and the last step's traces,
+    with odd and even step counts, with the launch schedule forced either way
+    (fused: the one-launch kernel runs at every degree and precision)."""
     import paper_1903_11521_amd as dg
-    _say(f"test_fused_step_equals_split N={N} prec={prec}")
+    _say(f"test_fused_step_equals_split N={N} prec={prec} fused={fused}")
     mesh, mats, Q, dt = dgtest.mesh_inputs(3, N, 11, relabel=True)
     plan = dg.Plan(N, prec)
+    default = plan.fuses_steps
+    assert default == (N <= 3)
+    plan.set_fusion(fused)
+    assert plan.fuses_steps == fused
+    from paper_1903_11521_amd import _lib as L
+    assert bool(L._load().dg_plan_fuses_steps(plan._h)) == fused
     star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
     E = mesh.E
     args = [plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot)]
@@ -219,10 +240,17 @@ def test_fused_step_equals_split(N, prec):
         plan.step_correct(Ib, tc, *args, Qb)
     assert torch.equal(Qa, Qb)
     assert torch.equal(ta, tc)
-    assert plan.fuses_steps == (N <= 3)
+    if fused and prec == 0:
+        # and the fused schedule against the oracle (3 steps)
+        rm = refmat.refmats(N)
+        ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+        ref = Q.copy()
+        for _ in range(3):
+            ref = stages.step(rm, dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+        assert_close(_host(Qa) - Q, ref - Q, 1e-12, "fused 3-step increment")
 
 
-@pytest.mark.parametrize("N", [3, 5])
+@pytest.mark.parametrize("N", [3, 5, 6])
 def test_plan_tune(N):
     """The launch-schedule tuner picks one of the two schedules, the plan
     reports it, and dg_step with two trace arrays still equals the split
@@ -248,33 +276,80 @@ def test_plan_tune(N):
     assert torch.equal(Qa, Qb)
 
 
-def test_full_size_config1_sampled():
-    """Degree 5 on the 40x40x40x6 = 384000-element mesh, one step in the launch
-    configuration the benchmark times; 96 sampled elements re-stepped by the
-    oracle (predictor on them and their neighbours)."""
+def test_debug_neighbour_checks():
+    """With the debug checks on, a neighbour index outside [-1, E) is rejected
+    synchronously (nothing enqueued); with them off it is treated like -1."""
     import paper_1903_11521_amd as dg
-    N = 5
-    _say("test_full_size_config1_sampled")
-    mesh, mats, Q, dt = dgtest.mesh_inputs(40, N, 1)
-    E = mesh.E
+    from paper_1903_11521_amd import _lib as L
+    N = 3
+    mesh, mats, Q, dt = dgtest.mesh_inputs(3, N, 13)
     plan = dg.Plan(N, 0)
     star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    E = mesh.E
+    bad = mesh.neigh.copy()
+    bad[E // 2, 1] = E            # one past the end
+    args = [plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(bad), _dev(mesh.face_rot)]
     Qg = _dev(Q)
     I = torch.empty(plan.dof_shape(E), dtype=torch.float64, device="cuda:0")
     tr = torch.empty(plan.trace_shape(E), dtype=torch.float64, device="cuda:0")
-    plan.step(Qg, I, tr, plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh),
-              _dev(mesh.face_rot), dt, 1)
-    Q1 = _host(Qg)
+    prev = L.set_debug_checks(True)
+    try:
+        with pytest.raises(dg.DGError, match="neighbour index"):
+            plan.step(Qg, I, tr, *args, dt, 1)
+        with pytest.raises(dg.DGError, match="element %d face 1" % (E // 2)):
+            plan.step_correct(I, tr, *args, Qg)
+        assert torch.equal(Qg, _dev(Q))          # nothing ran
+    finally:
+        L.set_debug_checks(prev)
+    # checks off: the entry acts as "no neighbour", equal to an explicit -1
+    none = mesh.neigh.copy()
+    none[E // 2, 1] = -1
+    Qa, Qb = _dev(Q), _dev(Q)
+    plan.step(Qa, I, tr, *args, dt, 1)
+    plan.step(Qb, I, tr, args[0], args[1], args[2], _dev(none), args[4], dt, 1)
+    assert torch.equal(Qa, Qb)
+
+
+@pytest.fixture(scope="module")
+def config1_data():
+    """The 40x40x40x6 = 384000-element degree-5 workload and its element data
+    (built once for the full-size tests)."""
+    import paper_1903_11521_amd as dg
+    mesh, mats, Q, dt = dgtest.mesh_inputs(40, 5, 1)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
     rng = np.random.default_rng(5)
+    E = mesh.E
     ids = np.sort(np.concatenate([rng.choice(E, 90, replace=False), [0, 1, 2, E - 3, E - 2, E - 1]]))
     ostar, oAp, oAm = dgtest.oracle_element_data_subset(mesh, mats, ids)
-    ref = stages.step_subset(refmat.refmats(N), dt, ids, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface,
-                             mesh.orient)
-    assert dgtest.rel_err(Q1[ids] - Q[ids], ref - Q[ids]) <= 1e-12
-    # two steps with the benchmark's arguments (second trace array) equal two
-    # split steps bitwise at this size
-    args = (plan.pack_star(_dev(star)), _dev(Ap), _dev(Am), _dev(mesh.neigh), _dev(mesh.face_rot))
-    Qa, Qb = _dev(Q), _dev(Q)
+    rm = refmat.refmats(5)
+    ref1 = stages.step_subset(rm, dt, ids, Q, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
+    return dict(mesh=mesh, mats=mats, Q=Q, dt=dt, star=star, Ap=Ap, Am=Am, ids=ids, ref1=ref1)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_full_size_config1_sampled(config1_data, prec):
+    """Degree 5 on the 40x40x40x6 = 384000-element mesh, one step in the launch
+    configuration the benchmark times (second trace array); 96 sampled
+    elements re-stepped by the oracle (predictor on them and their
+    neighbours), in every precision."""
+    import paper_1903_11521_amd as dg
+    _say(f"test_full_size_config1_sampled prec={prec}")
+    c = config1_data
+    mesh, Q, dt, ids = c["mesh"], c["Q"], c["dt"], c["ids"]
+    E = mesh.E
+    plan = dg.Plan(5, prec)
+    Qg = _dev(Q, plan.dtype)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device="cuda:0")
+    tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device="cuda:0")
+    args = (plan.pack_star(_dev(c["star"])), _dev(c["Ap"]), _dev(c["Am"]), _dev(mesh.neigh), _dev(mesh.face_rot))
+    plan.step(Qg, I, tr, *args, dt, 1, traces_b=torch.empty_like(tr))
+    Q1 = _host(Qg)
+    ref = c["ref1"]
+    Qr = _rounded(Q[ids], prec)
+    assert_close(Q1[ids] - Qr, ref - Q[ids], TOL_INC[prec], "sampled step increment")
+    assert_close(Q1[ids], ref, TOL[prec], "sampled Q^{n+1}")
+    # two steps with the benchmark's arguments equal two split steps bitwise
+    Qa, Qb = _dev(Q, plan.dtype), _dev(Q, plan.dtype)
     plan.step(Qa, I, tr, *args, dt, 2, traces_b=torch.empty_like(tr))
     for _ in range(2):
         plan.step_predict(Qb, args[0], dt, I, tr)
@@ -295,7 +370,7 @@ def _mesh_tensors(dg, N, n, seed_index, prec, relabel=True):
     return plan, m, (mesh, mats, Q, dt)
 
 
-@pytest.mark.parametrize("prec", [0, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_batch_mixed_degrees(prec):
     """Five meshes of degrees 2..6 stepped as one batch (graph replay): each
     mesh equals its own single-mesh dg_step bitwise, and the FP64 oracle."""
@@ -321,8 +396,9 @@ def test_batch_mixed_degrees(prec):
         ref = Q.copy()
         for _ in range(3):
             ref = stages.step(refmat.refmats(N), dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
-        Qin = Q.astype(np.float32).astype(np.float64) if prec else Q
-        assert dgtest.rel_err(_host(m["Q"]) - Qin, ref - Q) <= TOL[prec] * (30 if prec else 1)
+        Q3 = _host(m["Q"])
+        assert_close(Q3 - _rounded(Q, prec), ref - Q, TOL_INC[prec], "degree %d 3-step increment" % N)
+        assert_close(Q3, ref, TOL[prec], "degree %d Q after 3 steps" % N)
     batch.close()
 
 
@@ -340,7 +416,7 @@ def test_mixed_is_at_least_as_accurate_as_fp32():
         ref = Q.copy()
         for _ in range(3):
             ref = stages.step(refmat.refmats(N), dt, ref, ostar, oAp, oAm, mesh.neigh, mesh.nface, mesh.orient)
-        errs[prec] = dgtest.rel_err(_host(m["Q"]) - Q.astype(np.float32).astype(np.float64), ref - Q)
+        errs[prec] = dgtest.rel_err(_host(m["Q"]) - _rounded(Q, prec), ref - Q)
     _say("fp32 %.3e mixed %.3e" % (errs[1], errs[2]))
     assert errs[2] <= 1e-5 and errs[1] <= 1e-5
     assert errs[2] <= errs[1] * 1.5

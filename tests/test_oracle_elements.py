@@ -108,3 +108,30 @@ def test_flux_matrices_scaling_sign():
     An = np.einsum("esj,ejpq->espq", n, Jac)
     scale = -(2.0 * area / det[:, None])[..., None, None]
     assert np.allclose(Aplus + Aminus, scale * An, rtol=1e-10, atol=1e-10 * np.abs(scale * An).max())
+
+
+def test_face_without_neighbour_uses_own_material():
+    """A face with neigh = -1 takes the element's own material on the far
+    side: its A+ equals the homogeneous upwind flux, whose sum with the
+    matching A- is the (scaled) normal Jacobian; its A- is zero; other faces
+    are unchanged."""
+    mesh = cube_mesh(3, seed_for(4), relabel=True)
+    mats = _mats(mesh.E, 4)
+    nb = mesh.neigh.copy()
+    nb[0, 2] = -1
+    nb[5, 0] = -1
+    Ap, Am = elements.flux_matrices(mesh.X, mats, nb)
+    Ap0, Am0 = elements.flux_matrices(mesh.X, mats, mesh.neigh)
+    own = np.broadcast_to(mats[:, None, :], (mesh.E, 4, 3))
+    Ap_h, Am_h = elements.flux_matrices(mesh.X, mats, None, neighbour_materials=own)
+    _, det, _ = elements.geometry(mesh.X)
+    n, _, _, area = elements.face_frames(mesh.X)
+    rho, lam, mu = elements.lame(mats)
+    An = np.einsum("esj,ejpq->espq", n, elements.jacobians(rho, lam, mu))
+    for e, f in ((0, 2), (5, 0)):
+        assert np.all(Am[e, f] == 0.0)
+        assert np.array_equal(Ap[e, f], Ap_h[e, f])
+        ref = -(2.0 * area[e, f] / det[e]) * An[e, f]
+        assert np.allclose(Ap_h[e, f] + Am_h[e, f], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    mask = nb >= 0
+    assert np.array_equal(Ap[mask], Ap0[mask]) and np.array_equal(Am[mask], Am0[mask])
