@@ -28,7 +28,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-DTYPES = {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)"}
+DTYPES = {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)",
+          "bf16x3": "f32 storage, 3xbf16 matrix-core contractions (f64 flux solvers)"}
 
 
 def parse():
@@ -36,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "mixed", "bf16x3"], default="fp64")
     ap.add_argument("--degree", type=int, default=5)
     ap.add_argument("--n", type=int, default=40, help="cubes per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,7 +138,7 @@ def batched(args):
 
     import paper_1903_11521_amd as dg
     from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
-    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED, "bf16x3": dg.DG_BF16X3}[args.precision]
     rng = np.random.Generator(np.random.PCG64(seed_for(2)))
     sizes = np.exp(rng.uniform(np.log(10e3), np.log(200e3), args.meshes))
     degrees = rng.integers(2, 7, args.meshes)
@@ -202,7 +203,7 @@ def serving(args):
     from paper_1903_11521_amd.serving import GpuExecutor, Request, Server
     from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
     from math import comb
-    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED, "bf16x3": dg.DG_BF16X3}[args.precision]
     rng = np.random.Generator(np.random.PCG64(seed_for(4)))
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.requests))
     arrivals -= arrivals[0]
@@ -271,7 +272,7 @@ def main():
     from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
 
     N = args.degree
-    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED}[args.precision]
+    prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED, "bf16x3": dg.DG_BF16X3}[args.precision]
     plan = dg.Plan(N, prec)
     seed = seed_for(1)
     log("building mesh n=%d degree=%d" % (args.n, N))
@@ -323,7 +324,7 @@ def main():
     mean_s = lambda a, b: float(np.mean([ev[k][a].elapsed_time(ev[k][b]) for k in range(args.steps)])) * 1e-3
     t_pred, t_fused, t_corr = mean_s(0, 1), mean_s(1, 2), mean_s(2, 3)
     itemsize = 8 if prec == dg.DG_FP64 else 4
-    dtype = "f64" if prec == dg.DG_FP64 else "f32"
+    dtype = {dg.DG_FP64: "f64", dg.DG_BF16X3: "bf16x3"}.get(prec, "f32")
     counts = np.bincount(mesh.orient.ravel(), minlength=3) / mesh.orient.size
     sf = pm.stage_flops(N, counts)
     mb = pm.method_bytes(N, itemsize)
@@ -367,7 +368,7 @@ def main():
         "paper_context": "paper's best single-simulation O6 DP CPU figure: 1244 MDoF/s on 2x Xeon 8174 "
                          "(about 2.47 M element-updates/s, 15.3 % of NZ peak); context, not the target",
     }
-    if not args.no_stages:
+    if not args.no_stages and prec != dg.DG_BF16X3:
         log("per-stage timing")
         out["stages"] = time_stages(plan, E, Qg, star_p, Apg, Amg, neigh, face_rot, dt, sf, mb, dtype, stream)
     if not args.no_cpu_baseline:

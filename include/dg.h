@@ -29,8 +29,8 @@
  *                                  face block holds the face basis in parts
  *                                  of whole degree blocks, one part after the
  *                                  other, each part quantity major
- *                                  ([9][rows of the part]).  FP32 and mixed
- *                                  plans use one part ([9][Bf]); FP64 plans
+ *                                  ([9][rows of the part]).  FP32, mixed and
+ *                                  BF16X3 plans use one part ([9][Bf]); FP64 plans
  *                                  split the face basis into parts of at most
  *                                  16 rows (degree 5: rows [0,15), [15,21);
  *                                  degree 6: [0,15), [15,28)).
@@ -46,7 +46,7 @@
  *                                  face's first vertex in the neighbour's
  *                                  face triple)
  *   The element type of DOF arrays is double for DG_FP64 plans and float for
- *   DG_FP32 and DG_MIXED plans.
+ *   DG_FP32, DG_MIXED and DG_BF16X3 plans.
  *
  * Memory and streams: every array argument of the dg_* compute calls is a
  * DEVICE pointer owned by the caller; the library does not allocate, free or
@@ -78,8 +78,19 @@ typedef struct dg_plan dg_plan;
  * contraction in FP32 (flux solvers are read as FP64 and rounded).
  * DG_MIXED: FP32 DOFs and reference-matrix contractions; the Taylor time
  * integral is accumulated in FP64 and the flux-solver products run in FP64
- * (rounded once to FP32).  DOF-like arrays are float for FP32 and MIXED. */
-typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 2 } dg_precision;
+ * (rounded once to FP32).
+ * DG_BF16X3: FP32 DOFs and star matrices; every reference-matrix contraction
+ * runs on the matrix cores as three BF16 products, A_hi B_hi + A_hi B_lo +
+ * A_lo B_hi (x_hi = bf16(x), x_lo = bf16(x - x_hi), round to nearest even),
+ * accumulated in FP32, about 3 * 2^-16 relative error per product; the
+ * flux-solver products run in FP64 (rounded once to FP32); the Taylor scale
+ * factors dt/(k+1) and the dt*Q term of the time integral are formed in FP64
+ * and rounded once, the derivative terms added in FP32.  Only the step
+ * launches (dg_step, dg_step_predict, dg_step_correct, with
+ * two launches per step) and dg_pack_star exist for it; the per-stage calls,
+ * dg_step_fused's one-launch form and batches return DG_EUNSUPPORTED.
+ * DOF-like arrays are float for FP32, MIXED and BF16X3. */
+typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_MIXED = 2, DG_BF16X3 = 3 } dg_precision;
 
 typedef enum {
     DG_OK = 0,

@@ -11,6 +11,7 @@ import numpy as np
 DG_FP64 = 0
 DG_FP32 = 1
 DG_MIXED = 2
+DG_BF16X3 = 3
 
 
 class BatchItem(ctypes.Structure):

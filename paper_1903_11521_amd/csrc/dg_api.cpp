@@ -17,13 +17,6 @@
 #include "dg_internal.h"
 #include "refmat.h"
 
-struct dg_plan {
-    int degree;
-    dg_precision prec;
-    int B, Bf;
-    DgTable tab;
-};
-
 namespace {
 
 thread_local std::string g_err;
@@ -77,7 +70,7 @@ int check_neighbours(const int32_t *neigh, int64_t E, int64_t bound, hipStream_t
     } while (0)
 
 struct Tables {
-    DgTable t[3][7];   // [precision][degree]
+    DgTable t[4][7];   // [precision][degree]
     Tables()
     {
         std::memset(t, 0, sizeof t);
@@ -86,6 +79,12 @@ struct Tables {
         dg_table_4(&t[0][4], &t[1][4], &t[2][4]);
         dg_table_5(&t[0][5], &t[1][5], &t[2][5]);
         dg_table_6(&t[0][6], &t[1][6], &t[2][6]);
+        dg_mtable_2(&t[3][2]);
+        dg_mtable_3(&t[3][3]);
+        dg_mtable_4(&t[3][4]);
+        dg_mtable_5(&t[3][5]);
+        dg_mtable_6(&t[3][6]);
+        for (int n = 2; n <= 6; ++n) t[3][n].pack_star = t[1][n].pack_star;   // FP32 packed star
     }
 };
 
@@ -154,7 +153,7 @@ int dg_plan_create(int degree, dg_precision precision, dg_plan **out)
     if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
     *out = nullptr;
     if (degree < 2 || degree > 6) return fail(DG_EUNSUPPORTED, "degree %s%lld outside 2..6", "", degree);
-    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
+    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED && precision != DG_BF16X3)
         return fail(DG_EUNSUPPORTED, "unsupported precision %s%lld", "", (long long)precision);
     dg_plan *p = new (std::nothrow) dg_plan;
     if (!p) return fail(DG_ENOMEM, "out of host memory%s", "");
@@ -198,6 +197,7 @@ int dg_predictor(const dg_plan *plan, int64_t E, double dt, const void *Q, const
     CHECK_PTR(E, Q, "Q");
     CHECK_PTR(E, star_packed, "star_packed");
     CHECK_PTR(E, T, "T");
+    if (!plan->tab.predictor) return fail(DG_EUNSUPPORTED, "dg_predictor: not available for this precision%s", "");
     return hip_status(plan->tab.predictor(E, dt, Q, star_packed, T, s), "dg_predictor");
 }
 
@@ -207,6 +207,7 @@ int dg_time_integral(const dg_plan *plan, int64_t E, double dt, const void *T, v
     CHECK_E(E);
     CHECK_PTR(E, T, "T");
     CHECK_PTR(E, I, "I");
+    if (!plan->tab.time_integral) return fail(DG_EUNSUPPORTED, "dg_time_integral: not available for this precision%s", "");
     return hip_status(plan->tab.time_integral(E, dt, T, I, s), "dg_time_integral");
 }
 
@@ -217,6 +218,7 @@ int dg_volume(const dg_plan *plan, int64_t E, const void *I, const void *star_pa
     CHECK_PTR(E, I, "I");
     CHECK_PTR(E, star_packed, "star_packed");
     CHECK_PTR(E, Q, "Q");
+    if (!plan->tab.volume) return fail(DG_EUNSUPPORTED, "dg_volume: not available for this precision%s", "");
     return hip_status(plan->tab.volume(E, I, star_packed, Q, s), "dg_volume");
 }
 
@@ -227,6 +229,7 @@ int dg_local_flux(const dg_plan *plan, int64_t E, const void *I, const double *A
     CHECK_PTR(E, I, "I");
     CHECK_PTR(E, Aplus, "Aplus");
     CHECK_PTR(E, Q, "Q");
+    if (!plan->tab.local_flux) return fail(DG_EUNSUPPORTED, "dg_local_flux: not available for this precision%s", "");
     return hip_status(plan->tab.local_flux(E, I, Aplus, Q, s), "dg_local_flux");
 }
 
@@ -243,12 +246,29 @@ int dg_neighbour_flux(const dg_plan *plan, int64_t E, int64_t n_I, const void *I
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, Q, "Q");
     CHECK_NEIGH(neigh, E, n_I, s, "dg_neighbour_flux");
+    if (!plan->tab.neighbour_flux) return fail(DG_EUNSUPPORTED, "dg_neighbour_flux: not available for this precision%s", "");
     return hip_status(plan->tab.neighbour_flux(E, n_I, I, neigh, face_rot, Aminus, Q, s), "dg_neighbour_flux");
 }
 
 int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
             void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
             const int32_t *neigh, const uint8_t *face_rot, hipStream_t s)
+{
+    return dg_step_impl(plan, E, dt, n_steps, Q, I, traces, traces_b, star_packed, Aplus, Aminus, neigh,
+                        face_rot, s, true);
+}
+
+}  // extern "C"
+
+int dg_set_error(int code, const char *msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int dg_step_impl(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
+                 void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
+                 const int32_t *neigh, const uint8_t *face_rot, hipStream_t s, bool debug_checks)
 {
     CHECK_PLAN(plan);
     CHECK_E(E);
@@ -264,7 +284,7 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
     CHECK_PTR(E, Aminus, "Aminus");
     CHECK_PTR(E, neigh, "neigh");
     CHECK_PTR(E, face_rot, "face_rot");
-    CHECK_NEIGH(neigh, E, E, s, "dg_step");
+    if (debug_checks) CHECK_NEIGH(neigh, E, E, s, "dg_step");
     if (!traces_b || n_steps < 2 || !plan->tab.fuse_step) {
         const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
         for (int n = 0; n < n_steps; ++n) {
@@ -293,6 +313,8 @@ int dg_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, voi
     if (e != hipSuccess) return hip_status(e, "dg_step (correct)");
     return DG_OK;
 }
+
+extern "C" {
 
 int dg_step_predict(const dg_plan *plan, int64_t E, double dt, const void *Q, const void *star_packed, void *I,
                     void *traces, hipStream_t s)
@@ -364,6 +386,8 @@ int dg_plan_set_fusion(dg_plan *plan, int fused)
 {
     CHECK_PLAN(plan);
     if (fused != 0 && fused != 1) return fail(DG_EINVAL, "fusion mode %s%lld is neither 0 nor 1", "", fused);
+    if (fused == 1 && !plan->tab.step_fused)
+        return fail(DG_EUNSUPPORTED, "dg_plan_set_fusion: no fused step launch for this precision%s", "");
     plan->tab.fuse_step = fused == 1;
     return DG_OK;
 }
@@ -397,6 +421,7 @@ int dg_plan_tune(dg_plan *plan, int64_t E, hipStream_t s)
 {
     CHECK_PLAN(plan);
     if (E < 64 || E > ((int64_t)1 << 26)) return fail(DG_EINVAL, "tuning size %s%lld outside [64, 2^26]", "", E);
+    if (!plan->tab.step_fused) return 0;   // one schedule only (two launches)
     const size_t rs = plan->prec == DG_FP64 ? 8 : 4;
     const size_t nq = (size_t)E * 9 * plan->B, ntr = (size_t)E * 4 * 9 * plan->Bf;
     TuneBuffers b;
@@ -491,7 +516,7 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
     if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
     *out = nullptr;
     if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
-        return fail(DG_EUNSUPPORTED, "unsupported precision %s%lld", "", (long long)precision);
+        return fail(DG_EUNSUPPORTED, "unsupported batch precision %s%lld", "", (long long)precision);
     if (n_items < 0 || (n_items > 0 && !items)) return fail(DG_EINVAL, "bad item list%s", "");
     for (int i = 0; i < n_items; ++i) {
         const dg_batch_item &x = items[i];

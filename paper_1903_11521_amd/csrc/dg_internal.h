@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dg.h"
+
 // Host image of one mesh of a (batched) time step; layout identical to the
 // kernels' StepItem<real>.
 struct DgItem {
@@ -41,9 +43,34 @@ struct DgTable {
     hipError_t (*batch_correct)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);
 };
 
-// tables for DG_FP64, DG_FP32 and DG_MIXED
+// tables for DG_FP64, DG_FP32 and DG_MIXED (dg_launch.hip)
 void dg_table_2(DgTable *fp64, DgTable *fp32, DgTable *mixed);
 void dg_table_3(DgTable *fp64, DgTable *fp32, DgTable *mixed);
 void dg_table_4(DgTable *fp64, DgTable *fp32, DgTable *mixed);
 void dg_table_5(DgTable *fp64, DgTable *fp32, DgTable *mixed);
 void dg_table_6(DgTable *fp64, DgTable *fp32, DgTable *mixed);
+// tables for DG_BF16X3 (mfma_launch.hip); entries the form does not
+// implement are null
+void dg_mtable_2(DgTable *t);
+void dg_mtable_3(DgTable *t);
+void dg_mtable_4(DgTable *t);
+void dg_mtable_5(DgTable *t);
+void dg_mtable_6(DgTable *t);
+
+// A compiled (degree, precision) configuration (opaque dg_plan of dg.h).
+struct dg_plan {
+    int degree;
+    dg_precision prec;
+    int B, Bf;
+    DgTable tab;
+};
+
+// dg_step with its argument checks; debug_checks = false skips the
+// synchronous neighbour-table validation (which copies the table to host
+// memory).  The body of dg_step, shared with its variants.
+int dg_step_impl(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
+                 void *traces_b, const void *star_packed, const double *Aplus, const double *Aminus,
+                 const int32_t *neigh, const uint8_t *face_rot, hipStream_t s, bool debug_checks);
+
+// Sets the calling thread's dg_last_error text; returns code.
+int dg_set_error(int code, const char *msg);

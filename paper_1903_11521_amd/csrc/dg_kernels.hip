@@ -23,6 +23,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "dg_common.h"
 #include "dg_generated.h"
 
 namespace dgk {
@@ -40,17 +41,6 @@ template <typename real>
 constexpr int LB = CH<real> + 1;   // padded (odd) row stride of a column in LDS
 constexpr int NCOL = 8 * NQ;
 
-__host__ __device__ constexpr int nb3(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
-__host__ __device__ constexpr int nb2(int n) { return (n + 1) * (n + 2) / 2; }
-
-template <int I, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (I < E) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, E>(f);
-    }
-}
 
 // q-columns read by row p of the packed star matrix (elastic pattern:
 // stress rows couple to velocities, velocity rows to stresses)
@@ -76,15 +66,6 @@ struct Lane {
     real *own;      // this lane's column in buf
 };
 
-// XCD-aware block order: the hardware deals consecutive workgroups round
-// robin to the 8 XCDs; remapping makes each XCD (own L2) walk a contiguous
-// range of elements, which keeps face neighbours in the same L2.
-__device__ __forceinline__ int64_t logical_block()
-{
-    const int64_t nb = gridDim.x, b = blockIdx.x;
-    const int64_t full = (nb >> 3) << 3;
-    return b < full ? (b & 7) * (nb >> 3) + (b >> 3) : b;
-}
 
 template <typename real>
 __device__ __forceinline__ Lane<real> make_lane(real *buf, int64_t E, int64_t lb)

@@ -22,7 +22,8 @@ from __future__ import annotations
 from math import comb
 
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # vector FP64 and FP32 (MI355X datasheet)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3,   # vector FP64 and FP32 (MI355X datasheet)
+               "bf16x3": 2500.0 / 3}       # dense BF16 matrix cores, three products per useful one
 
 # Non-zero flops per element-update implied by the paper's SeisSol runs
 # (NZ GFLOPS / (MDoF/s / (9 B))), orders 3..7 = degrees 2..6.
