@@ -86,7 +86,7 @@ typedef struct dg_plan dg_plan;
  * flux-solver products run in FP64 (rounded once to FP32); the Taylor scale
  * factors dt/(k+1) and the dt*Q term of the time integral are formed in FP64
  * and rounded once, the derivative terms added in FP32.  Only the step
- * launches (dg_step, dg_step_predict, dg_step_correct, with
+ * launches (dg_step, dg_step_predict, dg_step_correct, dg_step_noalloc, with
  * two launches per step) and dg_pack_star exist for it; the per-stage calls,
  * dg_step_fused's one-launch form and batches return DG_EUNSUPPORTED.
  * DOF-like arrays are float for FP32, MIXED and BF16X3. */
@@ -262,6 +262,35 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
 /* n_steps time steps of every mesh of the batch, stream ordered. */
 int dg_batch_step(dg_batch *batch, int n_steps, hipStream_t stream);
 int dg_batch_destroy(dg_batch *batch);
+
+/* ---- stepping without device allocation ------------------------------ */
+
+/* Size in bytes of the library's fixed per-device face-trace buffer used by
+ * dg_step_noalloc (256 MiB). */
+#define DG_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dg_step
+ * without the caller's face-trace work arrays.  The traces live in a
+ * library-owned device buffer of DG_NOALLOC_SCRATCH_BYTES, one copy per
+ * device, held from the library's load until the process ends; its address
+ * on the current device is looked up on the first call on that device.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and skips the dg_set_debug_checks neighbour validation, which
+ * would copy the table to host memory.  Q, I and the static data are as for
+ * dg_step (I holds the last step's time integral on return); the result is
+ * bit for bit that of dg_step.  E times one trace array (E*4*9*Bf values of
+ * the plan's element type) must fit the buffer, else DG_EINVAL with the
+ * limit in dg_last_error and nothing enqueued (degree 5: 44 385 elements in
+ * FP64, 88 770 in FP32, mixed or BF16X3).  With two trace arrays' room, and where the
+ * plan fuses steps, one launch per step; otherwise two.  The buffer keeps the
+ * previous call's traces; every step writes all traces before any is read,
+ * so nothing needs clearing.  All calls on one device share the buffer:
+ * calls that overlap on a device (different streams, or threads without
+ * ordering) race and give wrong results. */
+int dg_step_noalloc(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I,
+                    const void *star_packed, const double *Aplus, const double *Aminus,
+                    const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
 
 /* Waits for the stream; reports asynchronous kernel failures as DG_EHIP. */
 int dg_sync(hipStream_t stream);

@@ -63,6 +63,7 @@ def _load():
         lib.dg_neighbour_flux.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_step_noalloc.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_plan_fuses_steps.argtypes = [vp]
         lib.dg_plan_tune.argtypes = [vp, i64, vp]
         lib.dg_plan_set_fusion.argtypes = [vp, i32]
@@ -322,6 +323,29 @@ class Plan:
                                self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
                                self._t(neigh, (E, 4), torch.int32, "neigh"),
                                self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
+        return Q
+
+    # bytes of the library's fixed face-trace buffer (DG_NOALLOC_SCRATCH_BYTES)
+    NOALLOC_SCRATCH_BYTES = 256 << 20
+
+    def noalloc_max_elements(self):
+        """Largest E that dg_step_noalloc accepts for this plan."""
+        rs = 8 if self.precision == DG_FP64 else 4
+        return self.NOALLOC_SCRATCH_BYTES // (4 * 9 * self.Bf * rs)
+
+    def step_noalloc(self, Q, I, star_packed, Aplus, Aminus, neigh, face_rot, dt, n_steps=1, stream=None):
+        """dg_step with the face traces in the library's fixed device buffer
+        (no device allocation; E up to noalloc_max_elements())."""
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_step_noalloc(self._h, E, float(dt), int(n_steps),
+                                       self._t(Q, self.dof_shape(E), self.dtype, "Q"),
+                                       self._t(I, self.dof_shape(E), self.dtype, "I"),
+                                       self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                       self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                                       self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                                       self._t(neigh, (E, 4), torch.int32, "neigh"),
+                                       self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
         return Q
 
     def step_predict(self, Q, star_packed, dt, I, traces, stream=None):

@@ -110,7 +110,7 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
         cmds.append([HIPCC] + HIP_FLAGS + ["-DDG_DEGREE=%d" % n, "-Rpass-analysis=kernel-resource-usage",
                                            "-c", os.path.join(CSRC, "mfma_launch.hip"), "-o", o])
         objs.append(o)
-    for src in ("dg_api.cpp", "refmat.cpp", "elements.cpp"):
+    for src in ("dg_api.cpp", "refmat.cpp", "elements.cpp", "dg_noalloc.hip"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o").replace(".hip", ".o"))
         cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
