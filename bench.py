@@ -227,7 +227,7 @@ def serving(args):
 
     free, _ = torch.cuda.mem_get_info()
     itemsize = 8 if prec == dg.DG_FP64 else 4
-    srv = Server(GpuExecutor(prec), int(0.8 * free), itemsize)
+    srv = Server(GpuExecutor(prec), int(0.8 * free), itemsize, log=log)
     for i in range(args.requests):
         srv.submit(make(i))
     log("serving %d requests at %.1f req/s" % (args.requests, args.rate))

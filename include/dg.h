@@ -253,14 +253,25 @@ typedef struct {
 typedef struct dg_batch dg_batch;
 
 /* Builds the work tables of a batch (device memory owned by the batch; this
- * call allocates and copies synchronously).  One time step of a batch is one
- * predictor launch and one corrector launch per degree present, over all
+ * call allocates, and uploads on a private stream that it waits for).  One
+ * time step of a batch is one predictor launch and one corrector launch per
+ * degree present, over all
  * meshes of that degree; the launches of a step are recorded once into a HIP
  * graph and replayed.  Each element's arithmetic is identical to dg_step's,
  * so a mesh gives bitwise the same result alone and in any batch. */
 int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out);
 /* n_steps time steps of every mesh of the batch, stream ordered. */
 int dg_batch_step(dg_batch *batch, int n_steps, hipStream_t stream);
+/* Replaces the batch's mesh list (continuous batching: meshes join and
+ * leave between steps).  Steps enqueued after this call step the new list;
+ * steps enqueued before it still read the old one.  The batch keeps two
+ * copies of its work tables and step graph and writes the one not used by
+ * the latest dg_batch_step, after the replays that used it have finished
+ * (a host wait on that slot only, not on the device); the tables are
+ * uploaded on a private stream and the step graph is recorded again.  No
+ * device-wide synchronisation.  Meshes that stay in the batch give bitwise
+ * the same results as before the update. */
+int dg_batch_update(dg_batch *batch, const dg_batch_item *items, int n_items);
 int dg_batch_destroy(dg_batch *batch);
 
 /* ---- stepping without device allocation ------------------------------ */

@@ -73,6 +73,7 @@ def _load():
         lib.dg_sync.argtypes = [vp]
         lib.dg_batch_create.argtypes = [i32, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(vp)]
         lib.dg_batch_step.argtypes = [vp, i32, vp]
+        lib.dg_batch_update.argtypes = [vp, ctypes.POINTER(BatchItem), i32]
         lib.dg_batch_destroy.argtypes = [vp]
         _lib = lib
         return lib
@@ -396,11 +397,18 @@ class Batch:
 
     def __init__(self, precision, meshes):
         lib = _load()
-        torch = _torch()
         self.precision = precision
-        dt_ = torch.float64 if precision == DG_FP64 else torch.float32
+        arr, keep = self._items(meshes)
+        h = ctypes.c_void_p()
+        _check(lib.dg_batch_create(precision, arr, len(meshes), ctypes.byref(h)))
+        self._h = h
+        self._keep = [keep]
+        self.elements = sum(int(m["E"]) for m in meshes)
+
+    def _items(self, meshes):
+        torch = _torch()
+        dt_ = torch.float64 if self.precision == DG_FP64 else torch.float32
         arr = (BatchItem * max(1, len(meshes)))()
-        self._keep = []
         for i, m in enumerate(meshes):
             N, E = int(m["degree"]), int(m["E"])
             B, Bf = comb(N + 3, 3), comb(N + 2, 2)
@@ -413,10 +421,16 @@ class Batch:
                                chk(m["Aminus"], (E, 4, 9, 9), torch.float64, "Aminus"),
                                chk(m["neigh"], (E, 4), torch.int32, "neigh"),
                                chk(m["face_rot"], (E, 4), torch.uint8, "face_rot"))
-            self._keep.append(m)
-        h = ctypes.c_void_p()
-        _check(lib.dg_batch_create(precision, arr, len(meshes), ctypes.byref(h)))
-        self._h = h
+        return arr, list(meshes)
+
+    def update(self, meshes):
+        """Replace the mesh list (dg_batch_update): steps enqueued from now on
+        step `meshes`; steps already enqueued keep their list.  The tensors of
+        the previous list stay referenced until the update after next (by
+        then no enqueued step reads them)."""
+        arr, keep = self._items(meshes)
+        _check(_load().dg_batch_update(self._h, arr, len(meshes)))
+        self._keep = (self._keep + [keep])[-2:]
         self.elements = sum(int(m["E"]) for m in meshes)
 
     def step(self, n_steps=1, stream=None):

@@ -96,27 +96,32 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
     codegen_mfma.generate(host, os.path.join(GEN, "mfma_tables.h"))
     objs = []
     cmds = []
-    headers = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".h", ".inc", ".hip"))]
-    headers += [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))]
-    headers.append(os.path.join(GEN, "dg_generated.h"))
-    headers.append(os.path.join(GEN, "mfma_tables.h"))
+    deps = {}    # object -> the sources and headers it is built from
+    c = lambda *names: [os.path.join(CSRC, n) for n in names]
+    gen_sparse = [os.path.join(GEN, "dg_generated.h")]
+    gen_mfma = [os.path.join(GEN, "mfma_tables.h")]
+    pub = [os.path.join(ROOT, "include", "dg.h")]
     for n in DEGREES:
         o = os.path.join(BUILD, "dg_launch_%d.o" % n)
         cmds.append([HIPCC] + HIP_FLAGS + ["-DDG_DEGREE=%d" % n, "-Rpass-analysis=kernel-resource-usage",
                                            "-c", os.path.join(CSRC, "dg_launch.hip"), "-o", o])
+        deps[o] = c("dg_launch.hip", "dg_kernels.hip", "dg_common.h", "dg_tables.h", "step_predict_body.inc",
+                    "step_correct_body.inc") + gen_sparse
         objs.append(o)
     for n in DEGREES:
         o = os.path.join(BUILD, "mfma_launch_%d.o" % n)
         cmds.append([HIPCC] + HIP_FLAGS + ["-DDG_DEGREE=%d" % n, "-Rpass-analysis=kernel-resource-usage",
                                            "-c", os.path.join(CSRC, "mfma_launch.hip"), "-o", o])
+        deps[o] = c("mfma_launch.hip", "mfma_kernels.hip", "dg_common.h", "dg_tables.h") + gen_mfma
         objs.append(o)
     for src in ("dg_api.cpp", "refmat.cpp", "elements.cpp", "dg_noalloc.hip"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o").replace(".hip", ".o"))
         cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        deps[o] = c(src, "dg_internal.h", "dg_tables.h", "refmat.h") + pub
         objs.append(o)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:
-        outs = list(ex.map(lambda c: _compile(c, [c[c.index("-c") + 1]] + headers, incremental), cmds))
+        outs = list(ex.map(lambda cmd: _compile(cmd, deps[cmd[cmd.index("-o") + 1]], incremental), cmds))
     usage = kernel_usage("\n".join(outs))
     spills = {k: v for k, v in usage.items() if v.get("ScratchSize", 0) > 0}
     # the sparse-FMA family must not spill; the matrix-core family's spills

@@ -484,39 +484,55 @@ int dg_plan_tune(dg_plan *plan, int64_t E, hipStream_t s)
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
+// A batch keeps two table slots.  Each holds, per degree present, the device
+// item array and block-to-item table, and one step recorded into a HIP graph
+// over them.  dg_batch_step replays the current slot; dg_batch_update writes
+// the other slot (after the last replay that used it has finished), records
+// its graph and makes it current, so the steps already enqueued keep reading
+// the tables they were launched with and no device-wide wait is needed.
 struct dg_batch {
     struct Group {
         int degree = 0;
         DgTable tab{};
         DgItem *d_items = nullptr;
         int32_t *d_block_item = nullptr;
-        int64_t nblocks = 0;
+        size_t cap_items = 0, cap_blocks = 0;
+        int64_t n_items = 0, nblocks = 0;
+    };
+    struct Slot {
+        Group groups[7];           // by degree
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t last_use = nullptr;
+        bool used = false;         // last_use recorded at least once
+        bool empty = true;
     };
     dg_precision prec = DG_FP64;
-    std::vector<Group> groups;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipStream_t capture = nullptr;
+    Slot slot[2];
+    int cur = 0;
+    hipStream_t aux = nullptr;     // private stream: table uploads and capture
+    std::vector<DgItem> h_items;
+    std::vector<int32_t> h_blocks;
     ~dg_batch()
     {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (capture) (void)hipStreamDestroy(capture);
-        for (auto &g : groups) {
-            if (g.d_items) (void)hipFree(g.d_items);
-            if (g.d_block_item) (void)hipFree(g.d_block_item);
+        for (auto &sl : slot) {
+            if (sl.last_use) (void)hipEventSynchronize(sl.last_use);
+            if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+            if (sl.graph) (void)hipGraphDestroy(sl.graph);
+            if (sl.last_use) (void)hipEventDestroy(sl.last_use);
+            for (auto &g : sl.groups) {
+                if (g.d_items) (void)hipFree(g.d_items);
+                if (g.d_block_item) (void)hipFree(g.d_block_item);
+            }
         }
+        if (aux) (void)hipStreamDestroy(aux);
     }
 };
 
-extern "C" {
+namespace {
 
-int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out)
+int check_batch_items(const dg_batch_item *items, int n_items)
 {
-    if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
-    *out = nullptr;
-    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
-        return fail(DG_EUNSUPPORTED, "unsupported batch precision %s%lld", "", (long long)precision);
     if (n_items < 0 || (n_items > 0 && !items)) return fail(DG_EINVAL, "bad item list%s", "");
     for (int i = 0; i < n_items; ++i) {
         const dg_batch_item &x = items[i];
@@ -530,14 +546,64 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
         CHECK_PTR(x.E, x.Aminus, "item Aminus");
         CHECK_PTR(x.E, x.neigh, "item neigh");
         CHECK_PTR(x.E, x.face_rot, "item face_rot");
-        CHECK_NEIGH(x.neigh, x.E, x.E, nullptr, "dg_batch_create");
+        CHECK_NEIGH(x.neigh, x.E, x.E, nullptr, "dg_batch");
     }
-    std::unique_ptr<dg_batch> b(new (std::nothrow) dg_batch);
-    if (!b) return fail(DG_ENOMEM, "out of host memory%s", "");
-    b->prec = precision;
+    return DG_OK;
+}
+
+hipError_t ensure(void **p, size_t *cap, size_t bytes)
+{
+    if (*cap >= bytes && *p) return hipSuccess;
+    size_t n = *cap ? *cap : 256;
+    while (n < bytes) n *= 2;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n);
+    if (e != hipSuccess) return e;
+    if (*p) (void)hipFree(*p);   // only after the slot's last use has finished
+    *p = q;
+    *cap = n;
+    return hipSuccess;
+}
+
+hipError_t batch_enqueue(dg_batch::Slot &sl, hipStream_t s)
+{
+    for (auto &g : sl.groups) {
+        if (!g.nblocks) continue;
+        hipError_t e = g.tab.batch_predict(g.d_items, g.d_block_item, g.nblocks, s);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &g : sl.groups) {
+        if (!g.nblocks) continue;
+        hipError_t e = g.tab.batch_correct(g.d_items, g.d_block_item, g.nblocks, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Writes `items` into slot k (whose last replay must have finished) and
+// records its step graph.
+int batch_fill(dg_batch *b, int k, const dg_batch_item *items, int n_items)
+{
+    dg_batch::Slot &sl = b->slot[k];
+    if (sl.used) {
+        hipError_t e = hipEventSynchronize(sl.last_use);
+        if (e != hipSuccess) return hip_status(e, "dg_batch (slot wait)");
+    }
+    if (sl.exec) {
+        (void)hipGraphExecDestroy(sl.exec);
+        sl.exec = nullptr;
+    }
+    if (sl.graph) {
+        (void)hipGraphDestroy(sl.graph);
+        sl.graph = nullptr;
+    }
+    sl.empty = true;
     for (int deg = 2; deg <= 6; ++deg) {
-        std::vector<DgItem> hv;
-        std::vector<int32_t> bi;
+        dg_batch::Group &G = sl.groups[deg];
+        G.degree = deg;
+        G.tab = tables().t[b->prec][deg];
+        b->h_items.clear();
+        b->h_blocks.clear();
         int64_t nb = 0;
         for (int i = 0; i < n_items; ++i) {
             const dg_batch_item &x = items[i];
@@ -546,62 +612,91 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
                                   x.face_rot);
             it.first_block = nb;
             const int64_t blocks = (x.E + DG_ELEMENTS_PER_BLOCK - 1) / DG_ELEMENTS_PER_BLOCK;
-            for (int64_t k = 0; k < blocks; ++k) bi.push_back((int32_t)hv.size());
+            for (int64_t q = 0; q < blocks; ++q) b->h_blocks.push_back((int32_t)b->h_items.size());
             nb += blocks;
-            hv.push_back(it);
+            b->h_items.push_back(it);
         }
-        if (hv.empty()) continue;
         if (nb > 0x7fffffff) return fail(DG_EINVAL, "batch too large%s", "");
-        dg_batch::Group g;
-        g.degree = deg;
-        g.tab = tables().t[precision][deg];
-        g.nblocks = nb;
-        b->groups.push_back(g);
-        dg_batch::Group &G = b->groups.back();
-        hipError_t e = hipMalloc(&G.d_items, sizeof(DgItem) * hv.size());
-        if (e == hipSuccess) e = hipMalloc(&G.d_block_item, sizeof(int32_t) * bi.size());
-        if (e == hipSuccess) e = hipMemcpy(G.d_items, hv.data(), sizeof(DgItem) * hv.size(), hipMemcpyHostToDevice);
+        G.n_items = (int64_t)b->h_items.size();
+        G.nblocks = nb;
+        if (!nb) continue;
+        sl.empty = false;
+        hipError_t e = ensure(reinterpret_cast<void **>(&G.d_items), &G.cap_items, sizeof(DgItem) * b->h_items.size());
         if (e == hipSuccess)
-            e = hipMemcpy(G.d_block_item, bi.data(), sizeof(int32_t) * bi.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_status(e, "dg_batch_create");
+            e = ensure(reinterpret_cast<void **>(&G.d_block_item), &G.cap_blocks, sizeof(int32_t) * b->h_blocks.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(G.d_items, b->h_items.data(), sizeof(DgItem) * b->h_items.size(),
+                               hipMemcpyHostToDevice, b->aux);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(G.d_block_item, b->h_blocks.data(), sizeof(int32_t) * b->h_blocks.size(),
+                               hipMemcpyHostToDevice, b->aux);
+        // the host vectors are reused for the next degree: wait for this copy
+        if (e == hipSuccess) e = hipStreamSynchronize(b->aux);
+        if (e != hipSuccess) return hip_status(e, "dg_batch (tables)");
     }
+    if (sl.empty) return DG_OK;
+    // record one step into a graph on the private stream
+    hipError_t e = hipStreamBeginCapture(b->aux, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e, "dg_batch (capture)");
+    hipError_t le = batch_enqueue(sl, b->aux);
+    e = hipStreamEndCapture(b->aux, &sl.graph);
+    if (le != hipSuccess) return hip_status(le, "dg_batch (launch)");
+    if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_status(e, "dg_batch (instantiate)");
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out)
+{
+    if (!out) return fail(DG_EINVAL, "null pointer: %s", "out");
+    *out = nullptr;
+    if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
+        return fail(DG_EUNSUPPORTED, "unsupported batch precision %s%lld", "", (long long)precision);
+    int rc = check_batch_items(items, n_items);
+    if (rc != DG_OK) return rc;
+    std::unique_ptr<dg_batch> b(new (std::nothrow) dg_batch);
+    if (!b) return fail(DG_ENOMEM, "out of host memory%s", "");
+    b->prec = precision;
+    hipError_t e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+    for (auto &sl : b->slot)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.last_use, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_status(e, "dg_batch_create");
+    rc = batch_fill(b.get(), 0, items, n_items);
+    if (rc != DG_OK) return rc;
+    b->cur = 0;
     *out = b.release();
     return DG_OK;
 }
 
-static hipError_t batch_enqueue(dg_batch *b, hipStream_t s)
+int dg_batch_update(dg_batch *b, const dg_batch_item *items, int n_items)
 {
-    for (auto &g : b->groups) {
-        hipError_t e = g.tab.batch_predict(g.d_items, g.d_block_item, g.nblocks, s);
-        if (e != hipSuccess) return e;
-    }
-    for (auto &g : b->groups) {
-        hipError_t e = g.tab.batch_correct(g.d_items, g.d_block_item, g.nblocks, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (!b) return fail(DG_EINVAL, "null batch%s", "");
+    int rc = check_batch_items(items, n_items);
+    if (rc != DG_OK) return rc;
+    const int k = 1 - b->cur;
+    rc = batch_fill(b, k, items, n_items);
+    if (rc != DG_OK) return rc;
+    b->cur = k;
+    return DG_OK;
 }
 
 int dg_batch_step(dg_batch *b, int n_steps, hipStream_t s)
 {
     if (!b) return fail(DG_EINVAL, "null batch%s", "");
     if (n_steps < 0) return fail(DG_EINVAL, "negative step count%s %lld", "", n_steps);
-    if (n_steps == 0 || b->groups.empty()) return DG_OK;
-    if (!b->exec) {
-        // record one step into a graph on a private stream, then replay it
-        hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_status(e, "dg_batch_step (capture)");
-        hipError_t le = batch_enqueue(b, b->capture);
-        e = hipStreamEndCapture(b->capture, &b->graph);
-        if (le != hipSuccess) return hip_status(le, "dg_batch_step (launch)");
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return hip_status(e, "dg_batch_step (instantiate)");
-    }
+    dg_batch::Slot &sl = b->slot[b->cur];
+    if (n_steps == 0 || sl.empty) return DG_OK;
     for (int n = 0; n < n_steps; ++n) {
-        hipError_t e = hipGraphLaunch(b->exec, s);
+        hipError_t e = hipGraphLaunch(sl.exec, s);
         if (e != hipSuccess) return hip_status(e, "dg_batch_step");
     }
+    hipError_t e = hipEventRecord(sl.last_use, s);
+    if (e != hipSuccess) return hip_status(e, "dg_batch_step (event)");
+    sl.used = true;
     return DG_OK;
 }
 

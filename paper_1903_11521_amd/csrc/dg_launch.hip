@@ -4,7 +4,7 @@
 #include <type_traits>
 
 #include "dg_kernels.hip"
-#include "dg_internal.h"
+#include "dg_tables.h"
 
 #ifndef DG_DEGREE
 #error "DG_DEGREE must be defined"

@@ -2,7 +2,7 @@
 // degree (DG_DEGREE).  Compiled once per supported degree.
 #include <cstring>
 
-#include "dg_internal.h"
+#include "dg_tables.h"
 #include "mfma_kernels.hip"
 
 #ifndef DG_DEGREE

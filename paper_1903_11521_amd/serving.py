@@ -9,8 +9,10 @@ The loop
     stops at it so that it is served as soon as memory frees up;
   * keeps the DOFs and static data of admitted requests resident on the GPU;
   * steps all admitted requests together: one dg_batch step (one predictor
-    and one corrector launch per degree present, a replayed HIP graph), the
-    batch being rebuilt whenever a request joins or leaves;
+    and one corrector launch per degree present, a replayed HIP graph); when
+    a request joins or leaves, the batch's mesh list is replaced in stream
+    order (dg_batch_update: the batch's second table slot and graph), with no
+    device-wide synchronisation;
   * records, for every request, the completion time of each of its steps and
     returns the final DOFs when it finishes.
 Per-step latency of a request = time between its consecutive step
@@ -55,8 +57,9 @@ class Request:
 class Server:
     """Scheduling and accounting; the executor does the device work."""
 
-    def __init__(self, executor, budget_bytes: int, itemsize: int, clock=time.perf_counter):
+    def __init__(self, executor, budget_bytes: int, itemsize: int, clock=time.perf_counter, log=None):
         self.ex = executor
+        self.log = log                   # optional progress callback (one line per finished request)
         self.budget = int(budget_bytes)
         self.itemsize = itemsize
         self.clock = clock
@@ -136,6 +139,9 @@ class Server:
                 self.used -= footprint_bytes(req.E, req.degree, self.itemsize)
                 del self.active[rid]
                 self.done.append(req)
+                if self.log is not None:
+                    self.log("request %d done (%d elements, degree %d, %d steps) at %.2f s; %d finished"
+                             % (rid, req.E, req.degree, req.n_steps, t, len(self.done)))
 
     # -- metrics --------------------------------------------------------------
     def latencies(self):
@@ -207,12 +213,11 @@ class GpuExecutor:
 
     def rebuild(self, rids):
         self.history.append(sorted(rids))
-        if self.batch is not None:
-            self.torch.cuda.synchronize()        # the old graph may still be running
-            self.batch.close()
-            self.batch = None
-        if rids:
-            self.batch = self.dg.Batch(self.precision, [self.meshes[r] for r in rids])
+        meshes = [self.meshes[r] for r in rids]
+        if self.batch is None:
+            self.batch = self.dg.Batch(self.precision, meshes)
+        else:
+            self.batch.update(meshes)
 
     def step(self, rids):
         torch = self.torch
@@ -227,7 +232,9 @@ class GpuExecutor:
 
     def remove(self, req: Request):
         m = self.meshes.pop(req.rid)
-        return m["Q"].double().cpu().numpy()     # stream-ordered after its last step
+        # stream-ordered after its last step; the batch keeps the request's
+        # tensors referenced until no enqueued step can read them
+        return m["Q"].double().cpu().numpy()
 
     def finish(self):
         if self.batch is not None:
