@@ -43,9 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched", "serving"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused"], default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
-                         "serving: Poisson arrivals of ensemble requests")
+                         "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh")
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=16)
@@ -191,6 +191,71 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def fused(args):
+    """Fused simulations: 16 independent simulations on one degree-N mesh
+    (the n x n x n cube-split mesh of the single workload, random materials),
+    stepped together by dg_fused_step (split-BF16 form, one element and its
+    16 simulations per wave).  DOFs N(0,1) drawn on the device from a seeded
+    generator.  The metric counts simulation-element updates."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
+    from workload import cube_mesh, dt_from_mesh, random_materials, seed_for
+    N = args.degree
+    plan = dg.Plan(N, dg.DG_BF16X3)
+    seed = seed_for(1)
+    log("building mesh n=%d degree=%d (16 simulations)" % (args.n, N))
+    mesh = cube_mesh(args.n, seed)
+    E = mesh.E
+    mats = random_materials(E, seed)
+    dt = dt_from_mesh(mesh, mats)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    star_p = plan.pack_star(to(star))
+    Apg, Amg = to(Ap), to(Am)
+    del star, Ap, Am
+    neigh, face_rot = to(mesh.neigh), to(mesh.face_rot)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    Qg = torch.randn(plan.fused_dof_shape(E), generator=g, dtype=torch.float32, device=dev)
+    I = torch.empty(plan.fused_dof_shape(E), dtype=torch.float32, device=dev)
+    tr = torch.empty(plan.fused_trace_shape(E), dtype=torch.float32, device=dev)
+    S = plan.FUSED_SIMS
+    torch.cuda.synchronize()
+    log("warmup %d steps" % args.warmup)
+    plan.fused_step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.warmup)
+    plan.sync()
+    log("timed %d steps on %d elements x %d simulations" % (args.steps, E, S))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.fused_step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = E * S * args.steps / el
+    # method bytes per simulation-element update: DOF arrays per simulation,
+    # star, flux solvers and tables shared by the 16 simulations
+    q = 9 * plan.B * 4
+    shared = 81 * 4 + 2 * 4 * 81 * 8 + 4 * 4 + 4
+    per_update = 4 * q + shared / S
+    roof = pm.kernel_roofline(pm.PAPER_NZ_PER_UPDATE[N] * value * el / args.steps, per_update * E * S,
+                              el / args.steps, "bf16x3")
+    roof["traffic"] = None
+    roof["kernel"] = "whole fused step (predictor and corrector launch)"
+    roof["algorithmic_bytes_per_update"] = per_update
+    out = {"metric": "element-updates/s", "value": value, "unit": "simulation-element-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPES["bf16x3"], "data": "synthetic",
+           "config": {"workload": "fused simulations: %d simulations of the degree-%d elastic scheme on the "
+                                  "%dx%dx%dx6 = %d-element jittered periodic cube-split mesh, one launch pair "
+                                  "per step" % (S, N, args.n, args.n, args.n, E),
+                      "elements": E, "simulations": S, "degree": N},
+           "useful_gflops": pm.PAPER_NZ_PER_UPDATE[N] * value / 1e9, "roofline": roof}
+    print(json.dumps(out), flush=True)
+
+
 def serving(args):
     """Poisson arrivals of independent simulations: E ~ log-uniform[5k, 500k]
     elements (cube-split meshes), degree U{3..6}, U{50..500} steps, random
@@ -261,6 +326,8 @@ def main():
         return
     if args.workload == "batched":
         return batched(args)
+    if args.workload == "fused":
+        return fused(args)
     if args.workload == "serving":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"

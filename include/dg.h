@@ -234,6 +234,29 @@ int dg_step_fused(const dg_plan *plan, int64_t E, double dt, void *Q, void *I, c
                   void *traces_out, const void *star_packed, const double *Aplus, const double *Aminus,
                   const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
 
+/* ---- fused simulations -------------------------------------------------- */
+
+/* Number of simulations a fused step advances together. */
+#define DG_FUSED_SIMS 16
+
+/* n_steps time steps of DG_FUSED_SIMS independent simulations on one mesh:
+ * the extra simulation index s of the paper's multiple-simulation form
+ * (Sec. 3 and 5.1.1: every DOF tensor Q_kp gains an index s, Q_kps, and the
+ * element-local operators act on all s alike).  The simulations share the
+ * mesh, the star matrices and the flux solvers; they differ in their DOFs.
+ * Only for DG_BF16X3 plans (DG_EUNSUPPORTED otherwise): the reference
+ * matrices meet the 16 simulations of one element on the matrix cores, so a
+ * wave reads each element's star matrices, flux solvers and neighbour
+ * relation once for all 16.  Layouts (float, simulation index fastest):
+ *     Q, I    [E][9][B][16]
+ *     traces  [E][4][9][Bf][16]   (work array)
+ * and star_packed, Aplus, Aminus, neigh, face_rot as for dg_step.  Each
+ * simulation's result is bit for bit that of dg_step with the same plan on
+ * that simulation's DOFs.  E < 2^31. */
+int dg_fused_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
+                  const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
+                  const uint8_t *face_rot, hipStream_t stream);
+
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller

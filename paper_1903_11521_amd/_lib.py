@@ -64,6 +64,7 @@ def _load():
         lib.dg_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_step_noalloc.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_fused_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_plan_fuses_steps.argtypes = [vp]
         lib.dg_plan_tune.argtypes = [vp, i64, vp]
         lib.dg_plan_set_fusion.argtypes = [vp, i32]
@@ -347,6 +348,31 @@ class Plan:
                                        self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
                                        self._t(neigh, (E, 4), torch.int32, "neigh"),
                                        self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
+        return Q
+
+    # simulations advanced together by fused_step (DG_FUSED_SIMS)
+    FUSED_SIMS = 16
+
+    def fused_dof_shape(self, E):
+        return (E, 9, self.B, self.FUSED_SIMS)
+
+    def fused_trace_shape(self, E):
+        return (E, 4, 9, self.Bf, self.FUSED_SIMS)
+
+    def fused_step(self, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot, dt, n_steps=1, stream=None):
+        """n_steps time steps of 16 simulations on one mesh (dg_fused_step;
+        DG_BF16X3 plans): Q, I (E, 9, B, 16), traces (E, 4, 9, Bf, 16)."""
+        torch = _torch()
+        E = Q.shape[0]
+        _check(_load().dg_fused_step(self._h, E, float(dt), int(n_steps),
+                                     self._t(Q, self.fused_dof_shape(E), self.dtype, "Q"),
+                                     self._t(I, self.fused_dof_shape(E), self.dtype, "I"),
+                                     self._t(traces, self.fused_trace_shape(E), self.dtype, "traces"),
+                                     self._t(star_packed, (E, 9, 3, 3), self.dtype, "star_packed"),
+                                     self._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                                     self._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                                     self._t(neigh, (E, 4), torch.int32, "neigh"),
+                                     self._t(face_rot, (E, 4), torch.uint8, "face_rot"), self._stream(stream)))
         return Q
 
     def step_predict(self, Q, star_packed, dt, I, traces, stream=None):

@@ -376,6 +376,35 @@ int dg_step_fused(const dg_plan *plan, int64_t E, double dt, void *Q, void *I, c
     return hip_status(plan->tab.step_predict(it, s), "dg_step_fused (predict)");
 }
 
+int dg_fused_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q, void *I, void *traces,
+                  const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
+                  const uint8_t *face_rot, hipStream_t s)
+{
+    CHECK_PLAN(plan);
+    if (!plan->tab.fused_predict || !plan->tab.fused_correct)
+        return fail(DG_EUNSUPPORTED, "dg_fused_step: no fused-simulation form for this precision%s", "");
+    CHECK_E(E);
+    if (E > 0x7fffffff) return fail(DG_EINVAL, "dg_fused_step: element count too large%s %lld", "", (long long)E);
+    if (n_steps < 0) return fail(DG_EINVAL, "negative step count%s %lld", "", n_steps);
+    CHECK_PTR(E, Q, "Q");
+    CHECK_PTR(E, I, "I");
+    CHECK_PTR(E, traces, "traces");
+    CHECK_PTR(E, star_packed, "star_packed");
+    CHECK_PTR(E, Aplus, "Aplus");
+    CHECK_PTR(E, Aminus, "Aminus");
+    CHECK_PTR(E, neigh, "neigh");
+    CHECK_PTR(E, face_rot, "face_rot");
+    CHECK_NEIGH(neigh, E, E, s, "dg_fused_step");
+    const DgItem it = make_item(E, dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot);
+    for (int n = 0; n < n_steps; ++n) {
+        hipError_t e = plan->tab.fused_predict(it, s);
+        if (e != hipSuccess) return hip_status(e, "dg_fused_step (predict)");
+        e = plan->tab.fused_correct(it, s);
+        if (e != hipSuccess) return hip_status(e, "dg_fused_step (correct)");
+    }
+    return DG_OK;
+}
+
 int dg_plan_fuses_steps(const dg_plan *plan)
 {
     CHECK_PLAN(plan);

@@ -41,6 +41,10 @@ struct DgTable {
     // nblocks workgroups to its item
     hipError_t (*batch_predict)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);
     hipError_t (*batch_correct)(const DgItem *items, const int32_t *block_item, int64_t nblocks, hipStream_t s);
+    // fused simulations (16 per element, DOFs [E][9][B][16]): the two step
+    // launches; null where the precision has no fused form
+    hipError_t (*fused_predict)(const DgItem &it, hipStream_t s);
+    hipError_t (*fused_correct)(const DgItem &it, hipStream_t s);
 };
 
 // tables for DG_FP64, DG_FP32 and DG_MIXED (dg_launch.hip)

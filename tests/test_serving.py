@@ -113,9 +113,10 @@ def _gpu_request(dg, rid, n, N, steps, arrival):
 @pytest.mark.gpu
 def test_alone_equals_mixed_on_gpu():
     """Requests that arrive while others are on the GPU join the running
-    batch; each result is bitwise the same as the request served alone, and
-    one of them matches the FP64 oracle within the mixed form's bar (1e-5 on
-    the increment, as in the parity tests)."""
+    batch (dg_batch_update, no device-wide wait); each result is bitwise the
+    same as the request served alone, and every one matches the FP64 oracle
+    within the mixed form's bar (1e-5 on the increment, as in the parity
+    tests)."""
     pytest.importorskip("torch")
     import dgtest
     import paper_1903_11521_amd as dg
@@ -145,16 +146,16 @@ def test_alone_equals_mixed_on_gpu():
     # requests joined a batch that was already running
     sets = [set(h) for h in ex.history]
     assert any(len(a) < len(b) and a < b for a, b in zip(sets, sets[1:])), sets
-    # request 0 against the oracle: 12 FP64 oracle steps
-    rid, n, N, steps, _ = specs[0]
-    mesh = cube_mesh(n, seed_for(50 + rid))
-    mats = random_materials(mesh.E, seed_for(50 + rid))
-    Q0 = random_dofs(mesh.E, 9, refmat.n_basis(N), seed_for(50 + rid))
-    ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
-    ref = Q0.copy()
-    for _ in range(steps):
-        ref = stages.step(refmat.refmats(N), dt_from_mesh(mesh, mats), ref, ostar, oAp, oAm, mesh.neigh,
-                          mesh.nface, mesh.orient)
-    served = next(r for r in srv.done if r.rid == rid).result
-    dgtest.assert_close(served - Q0.astype(np.float32).astype(np.float64), ref - Q0, 1e-5,
-                        "served request vs oracle (12-step increment)")
+    # every served request against the FP64 oracle (its own number of steps)
+    for rid, n, N, steps, _ in specs:
+        mesh = cube_mesh(n, seed_for(50 + rid))
+        mats = random_materials(mesh.E, seed_for(50 + rid))
+        Q0 = random_dofs(mesh.E, 9, refmat.n_basis(N), seed_for(50 + rid))
+        ostar, oAp, oAm = dgtest.oracle_element_data(mesh, mats)
+        ref = Q0.copy()
+        for _ in range(steps):
+            ref = stages.step(refmat.refmats(N), dt_from_mesh(mesh, mats), ref, ostar, oAp, oAm, mesh.neigh,
+                              mesh.nface, mesh.orient)
+        served = next(r for r in srv.done if r.rid == rid).result
+        dgtest.assert_close(served - Q0.astype(np.float32).astype(np.float64), ref - Q0, 1e-5,
+                            "served request %d vs oracle (%d-step increment)" % (rid, steps))
