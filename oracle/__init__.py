@@ -17,4 +17,6 @@ Modules
             K-tilde, R, R-hat, f  (Sec. 5.1.1 matrix shapes; weak form Sec. 2)
   elements  geometry, star matrices, Godunov flux-solver matrices A+/A-
   stages    ctypes binding of the C loop nests + pure-Python brute-force sums
+  madness   the separable contraction of Sec. 7 (Eq. stock_mra): the paper's
+            six-step chain of one-index contractions, and the literal sum
 """
