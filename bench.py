@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness"], default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
                          "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh")
     ap.add_argument("--meshes", type=int, default=32)
@@ -256,6 +256,51 @@ def fused(args):
     print(json.dumps(out), flush=True)
 
 
+def madness(args):
+    """The separable contraction of Sec. 7 (Eq. stock_mra): batches of random
+    p x p x p tensors and operator pairs of rank q, FP64 and FP32, through
+    dg_mra_apply; useful GFLOP/s counts the 12 p^3 q non-zero flops of the
+    six-step chain per tensor (the paper's counting)."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1903)
+    rows = []
+    for dtype, name, sizes in ((torch.float64, "f64", (8, 16, 20)), (torch.float32, "f32", (8, 16, 24))):
+        for p in sizes:
+            for q in sorted({1, max(1, p // 2), p}):
+                nb = max(1, (1 << 27) // (p ** 3 * 8))          # about 128 MiB of tensors
+                S = torch.randn((nb, p, p, p), generator=g, dtype=dtype, device=dev)
+                ops = [torch.randn(sh, generator=g, dtype=dtype, device=dev) for sh in ((p, q), (q, p)) * 3]
+                R = torch.empty_like(S)
+                dg.mra_apply(S, *ops, R=R)
+                torch.cuda.synchronize()
+                reps = 5
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    dg.mra_apply(S, *ops, R=R)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t0) / reps
+                fl = 12.0 * p ** 3 * q * nb
+                nbytes = 2.0 * p ** 3 * nb * S.element_size()
+                roof = pm.kernel_roofline(fl, nbytes, el, "f64" if name == "f64" else "f32")
+                rows.append({"dtype": name, "p": p, "q": q, "tensors": nb, "ms": el * 1e3,
+                             "gflops": fl / el / 1e9, "bound": roof["bound"], "frac": roof["frac"]})
+                log("mra %s p=%d q=%d: %.1f GFLOP/s" % (name, p, q, fl / el / 1e9))
+                del S, R, ops
+    best = max(r["gflops"] for r in rows if r["dtype"] == "f64")
+    out = {"metric": "useful GFLOP/s", "value": best, "unit": "GFLOP/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 and f32", "data": "synthetic",
+           "config": {"workload": "separable contraction of Sec. 7 (Eq. stock_mra): batches of p^3 tensors, "
+                                  "rank-q operator pairs, p in 8..24, q in {1, p/2, p}"},
+           "madness": rows}
+    print(json.dumps(out), flush=True)
+
+
 def serving(args):
     """Poisson arrivals of independent simulations: E ~ log-uniform[5k, 500k]
     elements (cube-split meshes), degree U{3..6}, U{50..500} steps, random
@@ -328,6 +373,8 @@ def main():
         return batched(args)
     if args.workload == "fused":
         return fused(args)
+    if args.workload == "madness":
+        return madness(args)
     if args.workload == "serving":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"

@@ -257,6 +257,24 @@ int dg_fused_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *
                   const void *star_packed, const double *Aplus, const double *Aminus, const int32_t *neigh,
                   const uint8_t *face_rot, hipStream_t stream);
 
+/* ---- the separable contraction of Sec. 7 -------------------------------- */
+
+/* Largest tensor size p of dg_mra_apply (two p^3 tensors held in LDS). */
+#define DG_MRA_MAX_P_FP64 20
+#define DG_MRA_MAX_P_FP32 24
+
+/* Eq. stock_mra (the MADNESS kernel of Sec. 7) for a batch of nb tensors:
+ *     R_ijk = sum S_xyz X^L_xl X^R_li Y^L_ym Y^R_mj Z^L_zn Z^R_nk
+ * with i, j, k, x, y, z in 0..p-1 and l, m, n in 0..q-1 (1 <= q <= p), the six
+ * operator factors shared by the batch.  Device pointers, row major, element
+ * type double (DG_FP64) or float (DG_FP32):  S, R [nb][p][p][p];
+ * XL, YL, ZL [p][q];  XR, YR, ZR [q][p].  Evaluated as the paper's chain of
+ * six one-index contractions on the matrix cores, FP64 or FP32 throughout
+ * (products and sums), one workgroup per tensor.  p up to DG_MRA_MAX_P_FP64
+ * or DG_MRA_MAX_P_FP32 (DG_EUNSUPPORTED above). */
+int dg_mra_apply(dg_precision precision, int64_t nb, int p, int q, const void *S, const void *XL, const void *XR,
+                 const void *YL, const void *YR, const void *ZL, const void *ZR, void *R, hipStream_t stream);
+
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller

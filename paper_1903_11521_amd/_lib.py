@@ -65,6 +65,7 @@ def _load():
         lib.dg_step_fused.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_step_noalloc.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_fused_step.argtypes = [vp, i64, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_mra_apply.argtypes = [i32, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_plan_fuses_steps.argtypes = [vp]
         lib.dg_plan_tune.argtypes = [vp, i64, vp]
         lib.dg_plan_set_fusion.argtypes = [vp, i32]
@@ -469,3 +470,29 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# the separable contraction of Sec. 7 (Eq. stock_mra)
+# ---------------------------------------------------------------------------
+MRA_MAX_P = {DG_FP64: 20, DG_FP32: 24}
+
+
+def mra_apply(S, XL, XR, YL, YR, ZL, ZR, R=None, stream=None):
+    """R_ijk = sum S_xyz XL_xl XR_li YL_ym YR_mj ZL_zn ZR_nk for a batch S
+    (nb, p, p, p) of device tensors (float64 or float32); factors (p, q) and
+    (q, p) of the same dtype.  Returns R (dg_mra_apply)."""
+    torch = _torch()
+    nb, p = S.shape[0], S.shape[1]
+    q = XL.shape[1]
+    prec = DG_FP64 if S.dtype == torch.float64 else DG_FP32
+    if R is None:
+        R = torch.empty_like(S)
+    t = Plan._t
+    args = [t(None, S, (nb, p, p, p), S.dtype, "S")]
+    for name, m, sh in (("XL", XL, (p, q)), ("XR", XR, (q, p)), ("YL", YL, (p, q)), ("YR", YR, (q, p)),
+                        ("ZL", ZL, (p, q)), ("ZR", ZR, (q, p))):
+        args.append(t(None, m, sh, S.dtype, name))
+    args.append(t(None, R, (nb, p, p, p), S.dtype, "R"))
+    _check(_load().dg_mra_apply(prec, nb, p, q, *args, Plan._stream(stream)))
+    return R

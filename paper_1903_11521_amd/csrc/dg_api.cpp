@@ -405,6 +405,28 @@ int dg_fused_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *
     return DG_OK;
 }
 
+int dg_mra_apply(dg_precision precision, int64_t nb, int p, int q, const void *S, const void *XL, const void *XR,
+                 const void *YL, const void *YR, const void *ZL, const void *ZR, void *R, hipStream_t s)
+{
+    if (precision != DG_FP64 && precision != DG_FP32)
+        return fail(DG_EUNSUPPORTED, "dg_mra_apply: precision %s%lld is neither DG_FP64 nor DG_FP32", "",
+                    (long long)precision);
+    CHECK_E(nb);
+    if (nb > 0x7fffffff) return fail(DG_EINVAL, "dg_mra_apply: batch too large%s %lld", "", (long long)nb);
+    const int pmax = precision == DG_FP64 ? DG_MRA_MAX_P_FP64 : DG_MRA_MAX_P_FP32;
+    if (p < 1 || p > pmax) return fail(DG_EUNSUPPORTED, "dg_mra_apply: tensor size p=%s%lld outside the supported range", "", p);
+    if (q < 1 || q > p) return fail(DG_EINVAL, "dg_mra_apply: rank q=%s%lld outside 1..p", "", q);
+    CHECK_PTR(nb, S, "S");
+    CHECK_PTR(nb, R, "R");
+    CHECK_PTR(nb, XL, "XL");
+    CHECK_PTR(nb, XR, "XR");
+    CHECK_PTR(nb, YL, "YL");
+    CHECK_PTR(nb, YR, "YR");
+    CHECK_PTR(nb, ZL, "ZL");
+    CHECK_PTR(nb, ZR, "ZR");
+    return hip_status(dg_mra_launch(precision == DG_FP64, nb, p, q, S, XL, XR, YL, YR, ZL, ZR, R, s), "dg_mra_apply");
+}
+
 int dg_plan_fuses_steps(const dg_plan *plan)
 {
     CHECK_PLAN(plan);

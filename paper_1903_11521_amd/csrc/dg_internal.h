@@ -20,3 +20,7 @@ int dg_step_impl(const dg_plan *plan, int64_t E, double dt, int n_steps, void *Q
 
 // Sets the calling thread's dg_last_error text; returns code.
 int dg_set_error(int code, const char *msg);
+
+// MADNESS contraction launcher (mra_kernels.hip).
+hipError_t dg_mra_launch(bool fp64, int64_t nb, int p, int q, const void *S, const void *XL, const void *XR,
+                         const void *YL, const void *YR, const void *ZL, const void *ZR, void *R, hipStream_t s);
