@@ -258,9 +258,11 @@ def fused(args):
 
 def madness(args):
     """The separable contraction of Sec. 7 (Eq. stock_mra): batches of random
-    p x p x p tensors and operator pairs of rank q, FP64 and FP32, through
-    dg_mra_apply; useful GFLOP/s counts the 12 p^3 q non-zero flops of the
-    six-step chain per tensor (the paper's counting)."""
+    p x p x p tensors (1 GiB of inputs, resident in HBM) and operator pairs of
+    rank q, FP64 and FP32, through dg_mra_apply, timed with HIP events over 10
+    launches on the launch stream; useful GFLOP/s counts the 12 p^3 q non-zero
+    flops of the six-step chain per tensor (the paper's counting), GB/s the
+    tensors read and written once."""
     import torch
 
     import paper_1903_11521_amd as dg
@@ -270,29 +272,34 @@ def madness(args):
     g.manual_seed(1903)
     rows = []
     for dtype, name, sizes in ((torch.float64, "f64", (8, 16, 20)), (torch.float32, "f32", (8, 16, 24))):
+        elem = 8 if dtype == torch.float64 else 4
         for p in sizes:
             for q in sorted({1, max(1, p // 2), p}):
-                nb = max(1, (1 << 27) // (p ** 3 * 8))          # about 128 MiB of tensors
+                nb = max(1, (1 << 30) // (p ** 3 * elem))          # 1 GiB of input tensors
                 S = torch.randn((nb, p, p, p), generator=g, dtype=dtype, device=dev)
                 ops = [torch.randn(sh, generator=g, dtype=dtype, device=dev) for sh in ((p, q), (q, p)) * 3]
                 R = torch.empty_like(S)
                 dg.mra_apply(S, *ops, R=R)
                 torch.cuda.synchronize()
-                reps = 5
-                t0 = time.perf_counter()
+                reps = 10
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
                 for _ in range(reps):
                     dg.mra_apply(S, *ops, R=R)
+                e1.record()
                 torch.cuda.synchronize()
-                el = (time.perf_counter() - t0) / reps
+                el = e0.elapsed_time(e1) / 1e3 / reps
                 fl = 12.0 * p ** 3 * q * nb
-                nbytes = 2.0 * p ** 3 * nb * S.element_size()
-                roof = pm.kernel_roofline(fl, nbytes, el, "f64" if name == "f64" else "f32")
+                nbytes = 2.0 * p ** 3 * nb * elem
+                roof = pm.kernel_roofline(fl, nbytes, el, name)
                 rows.append({"dtype": name, "p": p, "q": q, "tensors": nb, "ms": el * 1e3,
-                             "gflops": fl / el / 1e9, "bound": roof["bound"], "frac": roof["frac"]})
-                log("mra %s p=%d q=%d: %.1f GFLOP/s" % (name, p, q, fl / el / 1e9))
+                             "gflops": fl / el / 1e9, "gbs": nbytes / el / 1e9, "bound": roof["bound"],
+                             "frac": roof["frac"]})
+                log("mra %s p=%d q=%d: %.3f ms, %.1f GFLOP/s, %.0f GB/s (%s bound, %.2f of peak)"
+                    % (name, p, q, el * 1e3, fl / el / 1e9, nbytes / el / 1e9, roof["bound"], roof["frac"]))
                 del S, R, ops
     best = max(r["gflops"] for r in rows if r["dtype"] == "f64")
-    out = {"metric": "useful GFLOP/s", "value": best, "unit": "GFLOP/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+    out = {"metric": "useful GFLOP/s", "value": best, "unit": "GFLOP/s", "n_gpus": 1, "steps": 10, "warmup": 1,
            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64 and f32", "data": "synthetic",
            "config": {"workload": "separable contraction of Sec. 7 (Eq. stock_mra): batches of p^3 tensors, "
