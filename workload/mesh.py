@@ -150,3 +150,58 @@ def dt_from_mesh(mesh: CubeMesh, materials: np.ndarray, factor: float = 0.1) -> 
         area += 0.5 * np.linalg.norm(np.cross(X[:, b] - X[:, a], X[:, c] - X[:, a]), axis=1)
     hmin = np.min(6.0 * vol / area)
     return float(factor * hmin / np.max(materials[:, 1]))
+
+
+def graded_cube_mesh(n: int, seed: int, ratio: float, jitter: float = 0.1, relabel: bool = False) -> CubeMesh:
+    """cube_mesh with the x coordinate mapped by g(x) = (r^x - 1) / (r - 1),
+    so cell widths along x grow geometrically by the factor r = ratio from
+    x = 0 to x = 1.  g fixes 0 and 1 and leaves y, z alone, so the periodic
+    faces stay congruent."""
+    m = cube_mesh(n, seed, jitter=jitter, relabel=relabel)
+    if ratio != 1.0:
+        X = m.X.copy()
+        X[..., 0] = (ratio ** X[..., 0] - 1.0) / (ratio - 1.0)
+        m = CubeMesh(n=m.n, h=m.h, X=X, V=m.V, neigh=m.neigh, nface=m.nface, orient=m.orient)
+    return m
+
+
+def element_time_steps(mesh: CubeMesh, materials: np.ndarray, factor: float = 0.1) -> np.ndarray:
+    """Per-element CFL time step factor * h_e / cp_e, h_e the insphere
+    diameter 6 V / (sum of face areas) of element e."""
+    X = mesh.X
+    e1, e2, e3 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]
+    vol = np.abs(np.einsum("ei,ei->e", e1, np.cross(e2, e3))) / 6.0
+    area = np.zeros(X.shape[0])
+    for (a, b, c) in FACE_VERTS:
+        area += 0.5 * np.linalg.norm(np.cross(X[:, b] - X[:, a], X[:, c] - X[:, a]), axis=1)
+    return factor * (6.0 * vol / area) / materials[:, 1]
+
+
+def rate2_clusters(dt_elem: np.ndarray, neigh: np.ndarray, max_clusters: int = 8):
+    """Time-step clusters of rate 2: element e goes to the largest c with
+    2^c dt0 <= dt_e (dt0 = min dt_e, c < max_clusters), then clusters are
+    lowered until face neighbours differ by at most one level.  Returns
+    (cluster int32 [E], dt0)."""
+    dt0 = float(np.min(dt_elem))
+    c = np.floor(np.log2(dt_elem / dt0) + 1e-12).astype(np.int64)
+    c = np.clip(c, 0, max_clusters - 1)
+    nb = np.where(neigh >= 0, neigh, np.arange(len(c))[:, None])
+    while True:
+        lim = np.min(c[nb], axis=1) + 1
+        new = np.minimum(c, lim)
+        if np.array_equal(new, c):
+            break
+        c = new
+    return c.astype(np.int32), dt0
+
+
+def permute_elements(mesh: CubeMesh, order: np.ndarray) -> CubeMesh:
+    """The same mesh with its elements renumbered: new element i is old
+    element order[i] (neighbour ids remapped, faces unchanged)."""
+    order = np.asarray(order, dtype=np.int64)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    nb = mesh.neigh[order]
+    neigh = np.where(nb >= 0, inv[np.maximum(nb, 0)], -1).astype(np.int32)
+    return CubeMesh(n=mesh.n, h=mesh.h, X=mesh.X[order], V=mesh.V[order], neigh=neigh,
+                    nface=mesh.nface[order], orient=mesh.orient[order])
