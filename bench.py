@@ -28,6 +28,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PRECISIONS = {"fp64": 0, "fp32": 1, "mixed": 2, "bf16x3": 3}     # dg_precision of include/dg.h
 DTYPES = {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 time integral and flux solvers)",
           "bf16x3": "f32 storage, 3xbf16 matrix-core contractions (f64 flux solvers)"}
 
@@ -43,9 +44,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness", "lts"],
+                    default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
-                         "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh")
+                         "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh; "
+                         "madness: the separable contraction of Sec. 7; lts: local against global time stepping")
+    ap.add_argument("--grading", type=float, default=64.0, help="lts: cell-width ratio across the graded mesh")
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=16)
@@ -256,6 +260,93 @@ def fused(args):
     print(json.dumps(out), flush=True)
 
 
+def lts(args):
+    """Local time stepping (Sec. 6.4, Table tab:loh1): time to solution of the
+    degree-N elastic scheme on a graded mesh (the n x n x n cube-split mesh
+    with cell widths growing geometrically by --grading along x, random
+    materials), elements in rate-2 clusters of their CFL steps, numbered
+    cluster by cluster (interior elements of a cluster before its boundary
+    elements).  One timed step is one LTS cycle (2^(C-1) steps of
+    the smallest cluster, every element advanced by the same simulated
+    time).  Global time stepping over the same simulated time needs 2^(C-1)
+    steps of dt0 for every element: timed with dg_step, and with the LTS
+    scheduler given a single cluster (its overhead against dg_step)."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from workload import (element_time_steps, graded_cube_mesh, permute_elements, random_materials,
+                          rate2_clusters, seed_for)
+    N = args.degree
+    prec = PRECISIONS[args.precision]
+    plan = dg.Plan(N, prec)
+    seed = seed_for(1)
+    log("building graded mesh n=%d ratio=%g degree=%d" % (args.n, args.grading, N))
+    mesh = graded_cube_mesh(args.n, seed, args.grading)
+    mats = random_materials(mesh.E, seed)
+    cl, dt0 = rate2_clusters(element_time_steps(mesh, mats), mesh.neigh)
+    # cluster by cluster, each cluster's interior elements before its boundary
+    bnd = np.any(cl[mesh.neigh] != cl[:, None], axis=1)
+    order = np.lexsort((bnd, cl))
+    mesh = permute_elements(mesh, order)
+    mats, cl = mats[order], cl[order]
+    E = mesh.E
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    star_p = plan.pack_star(to(star))
+    Apg, Amg = to(Ap), to(Am)
+    del star, Ap, Am
+    neigh, face_rot = to(mesh.neigh), to(mesh.face_rot)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    Qg = torch.randn(plan.dof_shape(E), generator=g, dtype=plan.dtype, device=dev)
+    L = dg.Lts(plan, cl, mesh.neigh, dt0)
+    C = L.n_clusters
+    sizes = np.bincount(cl, minlength=C).tolist()
+    log("clusters %s, %d element updates per cycle (global stepping: %d)" % (sizes, L.updates_per_cycle,
+                                                                            E << (C - 1)))
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        fn(reps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    L.advance(args.warmup, Qg, star_p, Apg, Amg, neigh, face_rot)
+    t_lts = timed(lambda k: L.advance(k, Qg, star_p, Apg, Amg, neigh, face_rot), args.steps)
+    log("LTS: %.3f ms per cycle" % (t_lts * 1e3))
+    # global time stepping over one cycle's simulated time
+    ticks = 1 << (C - 1)
+    I = torch.empty(plan.dof_shape(E), dtype=plan.dtype, device=dev)
+    tr = torch.empty(plan.trace_shape(E), dtype=plan.dtype, device=dev)
+    trb = torch.empty_like(tr)
+    plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt0, ticks, traces_b=trb)
+    t_gts = timed(lambda k: plan.step(Qg, I, tr, star_p, Apg, Amg, neigh, face_rot, dt0, ticks * k,
+                                      traces_b=trb), max(1, args.steps // 2))
+    log("GTS (fused step kernels): %.3f ms per cycle" % (t_gts * 1e3))
+    one = dg.Lts(plan, np.zeros(E, np.int32), mesh.neigh, dt0)
+    t_gts_stage = timed(lambda k: one.advance(ticks * k, Qg, star_p, Apg, Amg, neigh, face_rot),
+                        max(1, args.steps // 2))
+    log("GTS (one-cluster LTS schedule): %.3f ms per cycle" % (t_gts_stage * 1e3))
+    value = L.updates_per_cycle / t_lts
+    out = {"metric": "time-to-solution speed-up of LTS over GTS", "value": t_gts / t_lts, "unit": "x",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_lts * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPES[args.precision], "data": "synthetic",
+           "config": {"workload": "local time stepping, degree-%d elastic scheme on the %dx%dx%dx6 = %d-element "
+                                  "periodic cube-split mesh graded by %g along x, rate-2 clusters of the per-element "
+                                  "CFL steps; one step = one cycle" % (N, args.n, args.n, args.n, E, args.grading),
+                      "elements": E, "degree": N, "clusters": sizes},
+           "lts_element_updates_per_s": value, "lts_ms_per_cycle": t_lts * 1e3,
+           "gts_ms_per_cycle": t_gts * 1e3, "gts_one_cluster_lts_ms_per_cycle": t_gts_stage * 1e3,
+           "update_ratio": (E << (C - 1)) / L.updates_per_cycle}
+    print(json.dumps(out), flush=True)
+
+
 def madness(args):
     """The separable contraction of Sec. 7 (Eq. stock_mra): batches of random
     p x p x p tensors (1 GiB of inputs, resident in HBM) and operator pairs of
@@ -382,6 +473,8 @@ def main():
         return fused(args)
     if args.workload == "madness":
         return madness(args)
+    if args.workload == "lts":
+        return lts(args)
     if args.workload == "serving":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"

@@ -275,6 +275,47 @@ int dg_fused_step(const dg_plan *plan, int64_t E, double dt, int n_steps, void *
 int dg_mra_apply(dg_precision precision, int64_t nb, int p, int q, const void *S, const void *XL, const void *XR,
                  const void *YL, const void *YR, const void *ZL, const void *ZR, void *R, hipStream_t stream);
 
+/* ---- local time stepping ------------------------------------------------ */
+
+/* Clustered local time stepping of rate 2 (Sec. 6.4, Table tab:loh1 compares
+ * it with global time stepping).  Element e belongs to cluster cluster[e]
+ * and steps with dt0 * 2^cluster[e]; face neighbours must differ by at most
+ * one cluster, and elements must be numbered cluster by cluster
+ * (non-decreasing cluster ids).  Each step of an element is the ADER step of
+ * Eqs. seissol:derivative, seissol:timeint, seissol:correction_local and
+ * seissol:correction_neigh, except that the neighbour term integrates each
+ * neighbour's predicted solution over the element's own step: the
+ * neighbour's step integral (same cluster), the half of its Taylor expansion
+ * that the step covers (larger cluster), or the sum of its two step
+ * integrals (smaller cluster).  One cycle is 2^(C-1) steps of the smallest
+ * cluster, C the number of clusters (max cluster id + 1); after each cycle
+ * all elements are at the same time. */
+#define DG_LTS_MAX_CLUSTERS 16
+typedef struct dg_lts dg_lts;
+
+/* Builds the schedule: cluster ranges and, per cluster, the neighbours whose
+ * integrals it gathers.  cluster [E] and neigh [E][4] (indices in [-1, E))
+ * are HOST arrays, read during the call only.  Allocates the work arrays
+ * (Taylor-scaled derivatives [E][N+1][9][B] and three [E][9][B] arrays of
+ * the plan's storage type) in device memory owned by the handle.  Errors:
+ * DG_EUNSUPPORTED for a precision without per-stage kernels (DG_BF16X3),
+ * DG_EINVAL for unsorted clusters, ids outside [0, DG_LTS_MAX_CLUSTERS),
+ * neighbours two or more clusters apart or a non-positive dt0, DG_ENOMEM. */
+int dg_lts_create(const dg_plan *plan, int64_t E, const int32_t *cluster, const int32_t *neigh, double dt0,
+                  dg_lts **out);
+/* Number of clusters and element updates per cycle (sum over clusters of
+ * their size times 2^(C-1-c)); either output may be NULL. */
+int dg_lts_clusters(const dg_lts *lts, int *n_clusters, int64_t *updates_per_cycle);
+/* Advances Q [E][9][B] (device, updated in place) by n_cycles cycles on
+ * `stream`.  The static arrays are those of dg_step for the same E elements
+ * (device pointers, 16-byte aligned).  The handle's work arrays make
+ * concurrent calls on one handle race. */
+int dg_lts_advance(dg_lts *lts, int n_cycles, void *Q, const void *star_packed, const double *Aplus,
+                   const double *Aminus, const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
+/* Frees the handle and its device memory (after the caller's stream work
+ * that uses it has finished). */
+int dg_lts_destroy(dg_lts *lts);
+
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller

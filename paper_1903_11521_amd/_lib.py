@@ -77,6 +77,11 @@ def _load():
         lib.dg_batch_step.argtypes = [vp, i32, vp]
         lib.dg_batch_update.argtypes = [vp, ctypes.POINTER(BatchItem), i32]
         lib.dg_batch_destroy.argtypes = [vp]
+        lib.dg_lts_create.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dbl,
+                                      ctypes.POINTER(vp)]
+        lib.dg_lts_clusters.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        lib.dg_lts_advance.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        lib.dg_lts_destroy.argtypes = [vp]
         _lib = lib
         return lib
 
@@ -466,6 +471,50 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.dg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Lts:
+    """Clustered local time stepping of rate 2 on one mesh (dg_lts_*).
+    `cluster` (E,) int32 host array, non-decreasing (elements numbered
+    cluster by cluster), `neigh` (E, 4) int32 host array; cluster c steps with
+    dt0 * 2^c.  advance() takes the device arrays of dg_step for the mesh."""
+
+    def __init__(self, plan, cluster, neigh, dt0):
+        import numpy as np
+        lib = _load()
+        cl = np.ascontiguousarray(cluster, dtype=np.int32)
+        nb = np.ascontiguousarray(neigh, dtype=np.int32)
+        E = int(cl.shape[0])
+        if nb.shape != (E, 4):
+            raise ValueError("neigh has shape %s, expected (%d, 4)" % (nb.shape, E))
+        h = ctypes.c_void_p()
+        ip = ctypes.POINTER(ctypes.c_int32)
+        _check(lib.dg_lts_create(plan._h, E, cl.ctypes.data_as(ip), nb.ctypes.data_as(ip), float(dt0),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.plan = plan
+        self.E = E
+        nc, upc = ctypes.c_int(), ctypes.c_int64()
+        _check(lib.dg_lts_clusters(self._h, ctypes.byref(nc), ctypes.byref(upc)))
+        self.n_clusters = nc.value
+        self.updates_per_cycle = upc.value
+
+    def advance(self, n_cycles, Q, star_packed, Aplus, Aminus, neigh, face_rot, stream=None):
+        torch = _torch()
+        p, E = self.plan, self.E
+        args = [p._t(Q, p.dof_shape(E), p.dtype, "Q"), p._t(star_packed, (E, 9, 3, 3), p.dtype, "star_packed"),
+                p._t(Aplus, (E, 4, 9, 9), torch.float64, "Aplus"),
+                p._t(Aminus, (E, 4, 9, 9), torch.float64, "Aminus"),
+                p._t(neigh, (E, 4), torch.int32, "neigh"), p._t(face_rot, (E, 4), torch.uint8, "face_rot")]
+        _check(_load().dg_lts_advance(self._h, int(n_cycles), *args, Plan._stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.dg_lts_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -119,3 +119,38 @@ def test_flop_and_byte_models():
     assert abs(pm.step_roofline_rate(6) / 155.34e6 - 1) < 1e-3
     r = pm.kernel_roofline(135e3 * 1000, 17948 * 1000, 17948 * 1000 / 4e12)
     assert r["bound"] == "hbm" and abs(r["frac"] - 0.5) < 1e-12
+
+
+def test_lts_argument_errors():
+    """dg_lts_create rejects bad schedules before it touches the device."""
+    import numpy as np
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.dg_plan_create(3, 0, ctypes.byref(h)) == 0
+    ip = ctypes.POINTER(ctypes.c_int32)
+    out = ctypes.c_void_p()
+    neigh = np.array([[1, -1, -1, -1], [0, 2, -1, -1], [1, -1, -1, -1]], dtype=np.int32)
+
+    def create(cl, nb=neigh, dt0=1e-3, plan=h):
+        cl = np.ascontiguousarray(cl, dtype=np.int32)
+        return lib.dg_lts_create(plan, len(cl), cl.ctypes.data_as(ip), nb.ctypes.data_as(ip),
+                                 ctypes.c_double(dt0), ctypes.byref(out))
+    assert create([1, 0, 0]) == -1 and b"cluster by cluster" in lib.dg_last_error()
+    assert create([0, 0, 2], np.array([[1, -1, -1, -1], [0, 2, -1, -1], [1, -1, -1, -1]], np.int32)) == -1
+    assert b"more than one cluster" in lib.dg_last_error()
+    assert create([0, 0, 16]) == -1 and b"outside" in lib.dg_last_error()
+    assert create([0, 0, 1], dt0=0.0) == -1 and b"dt0" in lib.dg_last_error()
+    bad = neigh.copy()
+    bad[2, 3] = 3
+    assert create([0, 0, 1], bad) == -1 and b"neighbour" in lib.dg_last_error()
+    hb = ctypes.c_void_p()
+    assert lib.dg_plan_create(3, 3, ctypes.byref(hb)) == 0
+    assert create([0, 0, 1], plan=hb) == -2 and b"per-stage" in lib.dg_last_error()
+    assert lib.dg_lts_create(h, 0, None, None, ctypes.c_double(1e-3), ctypes.byref(out)) == 0
+    n, u = ctypes.c_int(), ctypes.c_int64()
+    assert lib.dg_lts_clusters(out, ctypes.byref(n), ctypes.byref(u)) == 0 and n.value == 0 and u.value == 0
+    assert lib.dg_lts_advance(out, 3, *([None] * 7)) == 0      # empty mesh: nothing to do
+    assert lib.dg_lts_destroy(out) == 0
+    assert lib.dg_lts_advance(None, 1, *([None] * 7)) == -1
+    lib.dg_plan_destroy(hb)
+    lib.dg_plan_destroy(h)
