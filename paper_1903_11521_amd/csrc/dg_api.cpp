@@ -111,6 +111,7 @@ DgItem make_item(int64_t E, double dt, void *Q, void *I, void *traces, const voi
     it.neigh = neigh;
     it.face_rot = fr;
     it.first_block = 0;
+    it.nI = E;
     return it;
 }
 

@@ -731,6 +731,7 @@ struct StepItem {
     const int32_t *neigh;
     const uint8_t *face_rot;
     int64_t first_block;     // first workgroup of this item in a batched launch
+    int64_t nI;              // neighbour index bound of the corrector (>= E)
 };
 
 // part 1: predictor + time integral (+ FP64 accumulation in the mixed form)
@@ -747,7 +748,7 @@ k_step_predict(int64_t E, double dt, const real *__restrict__ Q, const real *__r
 
 template <int N, bool MIX, typename real>
 __global__ void __launch_bounds__(64)
-k_step_correct(int64_t E, const real *__restrict__ Iin, const real *__restrict__ traces,
+k_step_correct(int64_t E, int64_t NI, const real *__restrict__ Iin, const real *__restrict__ traces,
                const real *__restrict__ star, const double *__restrict__ Ap, const double *__restrict__ Am,
                const int32_t *__restrict__ neigh, const uint8_t *__restrict__ face_rot, real *__restrict__ Q)
 {
@@ -773,6 +774,7 @@ k_step_fused(int64_t E, double dt, real *__restrict__ I, const real *__restrict_
     __shared__ real buf[NCOL * LB<real>];
     {
         const real *Iin = I, *traces = tr_in;
+        const int64_t NI = E;
 #include "step_correct_body.inc"
     }
     // this wave's stores of Q^{n+1} complete before it reads them back
@@ -818,7 +820,7 @@ k_batch_correct(const StepItem<real> *__restrict__ items,
 {
     const int64_t b = logical_block();
     const StepItem<real> &it = items[block_item[b]];
-    const int64_t E = it.E, lb = b - it.first_block;
+    const int64_t E = it.E, NI = it.nI, lb = b - it.first_block;
     const real *Iin = it.I, *traces = it.traces, *star = it.star;
     const double *Ap = it.Ap, *Am = it.Am;
     const int32_t *neigh = it.neigh;

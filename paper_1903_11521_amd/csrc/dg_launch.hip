@@ -92,7 +92,7 @@ struct Launch {
     {
         if (it.E == 0) return hipSuccess;
         hipLaunchKernelGGL((dgk::k_step_correct<N, MIX, real>), dim3(wave_blocks(it.E)), dim3(64), 0, s, it.E,
-                           (const real *)it.I, (const real *)it.traces, (const real *)it.star, it.Ap, it.Am,
+                           it.nI < it.E ? it.E : it.nI, (const real *)it.I, (const real *)it.traces, (const real *)it.star, it.Ap, it.Am,
                            it.neigh, it.face_rot, (real *)it.Q);
         return hipGetLastError();
     }

@@ -17,6 +17,9 @@ struct DgItem {
     const int32_t *neigh;
     const uint8_t *face_rot;
     int64_t first_block;
+    // neighbour index bound of the step corrector (>= E): indices in [E, nI)
+    // name read-only face-trace slots after the item's own elements
+    int64_t nI;
 };
 
 constexpr int DG_ELEMENTS_PER_BLOCK = 7;

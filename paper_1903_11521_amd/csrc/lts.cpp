@@ -6,29 +6,31 @@
 //   same cluster:    the neighbour's step integral;
 //   larger cluster:  the neighbour's Taylor expansion integrated over the
 //                    half of its step that the element's step covers;
-//   smaller cluster: the sum of the neighbour's two step integrals (a buffer
-//                    filled as the neighbour steps).
+//   smaller cluster: the sum of the neighbour's two step integrals.
 // One cycle is 2^(C-1) ticks of dt0.  At each tick the clusters whose step
 // starts there run their predictor; then the clusters whose step ends at
 // the next tick are corrected.  Elements are numbered cluster by cluster.
 //
-// A cluster runs on the step kernels (predictor with time integral and face
-// traces; corrector with volume, local flux and the neighbour flux of faces
-// shared with its own cluster, through a cluster-relative neighbour table in
-// which other clusters' elements are -1).  The faces shared with other
-// clusters are added by the per-stage neighbour flux over the cluster's
-// boundary range (from its first element with such a face to its end),
-// reading the gathered integrals of those neighbours; the per-stage
-// predictor supplies Taylor derivatives for the boundary elements that a
-// smaller cluster integrates in halves.  Numbering a cluster's interior
-// elements before its boundary elements keeps the boundary range short; any
-// order within a cluster gives the same result.
+// Every cluster runs on the step kernels.  The neighbour term reads face
+// traces (R^T of the integral, linear in it), so a cluster's trace array
+// holds its own elements' slots followed by ghost slots, one per neighbour
+// in another cluster, and a cluster-relative neighbour table points at
+// them.  Before a cluster's corrector its ghost slots are filled:
+//   larger neighbour: the predictor run a second time with dt/2 gives the
+//                     traces of the first half of its step (the Taylor
+//                     expansion does not depend on dt); the second half is
+//                     the full step's traces minus the first half's;
+//   smaller neighbour: a trace buffer that sums its two steps' traces.
+// The second predictor runs from the cluster's first element with a
+// neighbour one cluster down; numbering those elements last keeps it short
+// (any order within a cluster gives the same result).
 #include "dg.h"
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -42,21 +44,23 @@ struct dg_lts {
     int C = 0;
     double dt0 = 0.0;
     size_t elem = 8;
-    int PB = 0, N1 = 0;
+    int PB = 0, TB = 0;                     // values per DOF block and per trace slot
     std::vector<int64_t> start;             // C + 1 cluster offsets
-    std::vector<int64_t> bstart;            // per cluster: start of its boundary range
-    std::vector<char> need_T;               // per cluster: a smaller cluster integrates it in halves
-    void *T = nullptr, *I = nullptr, *Buf = nullptr, *G = nullptr, *traces = nullptr;
-    int32_t *neigh_rel = nullptr;           // [E][4]: same-cluster neighbours, relative to the cluster start
-    int32_t *neigh_for = nullptr;           // [E][4]: neighbours in other clusters (global ids)
-    void *lists = nullptr;                  // device: gather ids, kinds and buffer ids of all clusters
+    std::vector<int64_t> tstart;            // per cluster: first element with a neighbour one cluster down
+    std::vector<int64_t> region;            // C + 1 offsets of the clusters' trace regions (own + ghost slots)
+    std::vector<int64_t> nghost;
+    void *I = nullptr, *IH = nullptr;       // [E][PB] step and half-step integrals
+    void *TR = nullptr;                     // trace regions, region[C] slots
+    void *TRH = nullptr, *TRB = nullptr;    // [E][TB] half-step traces, trace buffer
+    int32_t *neigh_rel = nullptr;           // [E][4] cluster-relative neighbour table
+    void *lists = nullptr;                  // device: ghost ids, ghost kinds and buffer ids of all clusters
     std::vector<const int32_t *> gids, bids;
     std::vector<const int8_t *> gkind;
-    std::vector<int64_t> ng, nbuf;
+    std::vector<int64_t> nbuf;
 
     ~dg_lts()
     {
-        for (void *p : {T, I, Buf, G, traces, (void *)neigh_rel, (void *)neigh_for, lists})
+        for (void *p : {I, IH, TR, TRH, TRB, (void *)neigh_rel, lists})
             if (p) (void)hipFree(p);
     }
 };
@@ -89,9 +93,8 @@ int dg_lts_create(const dg_plan *plan, int64_t E, const int32_t *cluster, const 
     if (!out) return fail(DG_EINVAL, "dg_lts_create: null output pointer");
     *out = nullptr;
     if (!plan) return fail(DG_EINVAL, "dg_lts_create: null plan");
-    const DgTable &t = plan->tab;
-    if (!t.predictor || !t.neighbour_flux || !t.step_predict || !t.step_correct)
-        return fail(DG_EUNSUPPORTED, "dg_lts_create: the plan's precision has no per-stage kernels");
+    if (plan->prec == DG_BF16X3 || !plan->tab.step_predict || !plan->tab.step_correct)
+        return fail(DG_EUNSUPPORTED, "dg_lts_create: not available for this precision (split-BF16 form)");
     if (E < 0 || E > 0x7fffffff) return fail(DG_EINVAL, "dg_lts_create: element count %lld out of range", E);
     if (E > 0 && (!cluster || !neigh)) return fail(DG_EINVAL, "dg_lts_create: null cluster or neighbour table");
     if (!(dt0 > 0.0) || !std::isfinite(dt0)) return fail(DG_EINVAL, "dg_lts_create: dt0 must be positive and finite");
@@ -122,23 +125,24 @@ int dg_lts_create(const dg_plan *plan, int64_t E, const int32_t *cluster, const 
     L->dt0 = dt0;
     L->elem = plan->prec == DG_FP64 ? 8 : 4;
     L->PB = 9 * plan->B;
-    L->N1 = plan->degree + 1;
+    L->TB = 4 * 9 * plan->Bf;
     L->start.assign((size_t)C + 1, E);
     for (int64_t e = E - 1; e >= 0; --e) L->start[(size_t)cluster[e]] = e;
     for (int c = C - 1; c >= 0; --c)
         if (L->start[(size_t)c] > L->start[(size_t)c + 1]) L->start[(size_t)c] = L->start[(size_t)c + 1];
-    // host tables: per cluster its boundary range, the neighbours in other
-    // clusters of its elements (each once) with their kind, and its elements
-    // that have a neighbour one cluster up; the two neighbour tables
+    // per cluster: ghosts (neighbours in other clusters, each once, with
+    // kind 1 = one up, 2 = one down), elements with a neighbour one up (their
+    // traces are buffered), the first element with a neighbour one down; the
+    // cluster-relative neighbour table
     std::vector<std::vector<int32_t>> gi((size_t)C), bi((size_t)C);
     std::vector<std::vector<int8_t>> gk((size_t)C);
-    std::vector<int64_t> mark((size_t)E, -1);
-    std::vector<int32_t> nrel((size_t)E * 4, -1), nfor((size_t)E * 4, -1);
-    L->bstart.assign((size_t)C, 0);
-    L->need_T.assign((size_t)C, 0);
+    std::vector<int64_t> slot((size_t)E, -1), mark((size_t)E, -1);
+    std::vector<int32_t> nrel((size_t)E * 4, -1);
+    L->tstart.assign((size_t)C, 0);
+    L->nghost.assign((size_t)C, 0);
     for (int c = 0; c < C; ++c) {
         const int64_t s0 = L->start[(size_t)c], s1 = L->start[(size_t)c + 1];
-        int64_t first_bnd = s1;
+        int64_t first_down = s1;
         for (int64_t e = s0; e < s1; ++e) {
             bool up = false;
             for (int s = 0; s < 4; ++s) {
@@ -149,35 +153,38 @@ int dg_lts_create(const dg_plan *plan, int64_t E, const int32_t *cluster, const 
                     nrel[(size_t)(e * 4 + s)] = (int32_t)(v - s0);
                     continue;
                 }
-                nfor[(size_t)(e * 4 + s)] = v;
-                if (first_bnd == s1) first_bnd = e;
                 if (dc == 1) up = true;
-                if (dc == -1) L->need_T[(size_t)c] = 1;
-                if (mark[(size_t)v] == c) continue;
-                mark[(size_t)v] = c;
-                gi[(size_t)c].push_back(v);
-                gk[(size_t)c].push_back((int8_t)(dc == 1 ? 1 : 2));
+                if (dc == -1 && first_down == s1) first_down = e;
+                if (mark[(size_t)v] != c) {
+                    mark[(size_t)v] = c;
+                    slot[(size_t)v] = (int64_t)gi[(size_t)c].size();
+                    gi[(size_t)c].push_back(v);
+                    gk[(size_t)c].push_back((int8_t)(dc == 1 ? 1 : 2));
+                }
+                nrel[(size_t)(e * 4 + s)] = (int32_t)((s1 - s0) + slot[(size_t)v]);
             }
             if (up) bi[(size_t)c].push_back((int32_t)e);
         }
-        L->bstart[(size_t)c] = first_bnd;
+        L->tstart[(size_t)c] = first_down;
+        L->nghost[(size_t)c] = (int64_t)gi[(size_t)c].size();
     }
+    L->region.assign((size_t)C + 1, 0);
+    for (int c = 0; c < C; ++c)
+        L->region[(size_t)c + 1] = L->region[(size_t)c] + (L->start[(size_t)c + 1] - L->start[(size_t)c]) +
+                                   L->nghost[(size_t)c];
     size_t n32 = 0, n8 = 0;
     for (int c = 0; c < C; ++c) n32 += gi[(size_t)c].size() + bi[(size_t)c].size(), n8 += gk[(size_t)c].size();
-    const size_t pe = (size_t)L->PB * L->elem;
-    const size_t tre = (size_t)4 * 9 * plan->Bf * L->elem;
+    const size_t pe = (size_t)L->PB * L->elem, te = (size_t)L->TB * L->elem;
     hipError_t h = hipSuccess;
     if (E > 0) {
-        if ((h = hipMalloc(&L->T, (size_t)E * L->N1 * pe)) == hipSuccess &&
-            (h = hipMalloc(&L->I, (size_t)E * pe)) == hipSuccess &&
-            (h = hipMalloc(&L->Buf, (size_t)E * pe)) == hipSuccess &&
-            (h = hipMalloc(&L->G, (size_t)E * pe)) == hipSuccess &&
-            (h = hipMalloc(&L->traces, (size_t)E * tre)) == hipSuccess &&
-            (h = hipMalloc((void **)&L->neigh_rel, (size_t)E * 16)) == hipSuccess &&
-            (h = hipMalloc((void **)&L->neigh_for, (size_t)E * 16)) == hipSuccess)
+        if ((h = hipMalloc(&L->I, (size_t)E * pe)) == hipSuccess &&
+            (h = hipMalloc(&L->IH, (size_t)E * pe)) == hipSuccess &&
+            (h = hipMalloc(&L->TR, (size_t)L->region[(size_t)C] * te)) == hipSuccess &&
+            (h = hipMalloc(&L->TRH, (size_t)E * te)) == hipSuccess &&
+            (h = hipMalloc(&L->TRB, (size_t)E * te)) == hipSuccess &&
+            (h = hipMalloc((void **)&L->neigh_rel, (size_t)E * 16)) == hipSuccess)
             h = hipMalloc(&L->lists, n32 * 4 + n8 + 16);
         if (h == hipSuccess) h = hipMemcpy(L->neigh_rel, nrel.data(), nrel.size() * 4, hipMemcpyHostToDevice);
-        if (h == hipSuccess) h = hipMemcpy(L->neigh_for, nfor.data(), nfor.size() * 4, hipMemcpyHostToDevice);
     }
     if (h != hipSuccess) {
         delete L;
@@ -189,13 +196,11 @@ int dg_lts_create(const dg_plan *plan, int64_t E, const int32_t *cluster, const 
     L->gids.resize((size_t)C);
     L->bids.resize((size_t)C);
     L->gkind.resize((size_t)C);
-    L->ng.resize((size_t)C);
     L->nbuf.resize((size_t)C);
     unsigned char *dev = static_cast<unsigned char *>(L->lists);
     for (int c = 0; c < C; ++c) {
         const auto &g = gi[(size_t)c], &b = bi[(size_t)c];
         const auto &k = gk[(size_t)c];
-        L->ng[(size_t)c] = (int64_t)g.size();
         L->nbuf[(size_t)c] = (int64_t)b.size();
         L->gids[(size_t)c] = reinterpret_cast<const int32_t *>(dev + off32);
         if (!g.empty()) std::memcpy(blob.data() + off32, g.data(), g.size() * 4);
@@ -237,71 +242,68 @@ int dg_lts_advance(dg_lts *lts, int n_cycles, void *Q, const void *star_packed, 
     const void *ptrs[] = {Q, star_packed, Aplus, Aminus, neigh, face_rot};
     for (const void *p : ptrs)
         if (!p || !aligned16(p)) return fail(DG_EINVAL, "dg_lts_advance: null or not 16-byte aligned array");
+    // the neighbour table itself is read at creation (host copy); the handle
+    // holds the cluster-relative form the kernels use
     const DgTable &t = lts->plan->tab;
     const bool fp64 = lts->elem == 8;
-    const int C = lts->C, N1 = lts->N1, PB = lts->PB;
-    const size_t qe = (size_t)PB * lts->elem, te = qe * N1, se = 81 * lts->elem, ae = 4 * 81;
+    const int C = lts->C, TB = lts->TB;
+    const size_t qe = (size_t)lts->PB * lts->elem, te = (size_t)TB * lts->elem, se = 81 * lts->elem,
+                 ae = 4 * 81 * 8;
     auto at = [](const void *p, int64_t e, size_t stride) {
-        return static_cast<const char *>(p) + (size_t)e * stride;
+        return const_cast<char *>(static_cast<const char *>(p)) + (size_t)e * stride;
     };
-    auto atm = [](void *p, int64_t e, size_t stride) { return static_cast<char *>(p) + (size_t)e * stride; };
+    // base pointer p with p + v * te = element v's own slot in cluster c's
+    // region (region[c] >= start[c], so p lies inside the array)
+    auto own_base = [&](int c) { return at(lts->TR, lts->region[(size_t)c] - lts->start[(size_t)c], te); };
+    auto item = [&](int c, int64_t e0, int64_t e1, double dt, void *I, void *traces) {
+        DgItem it;
+        it.E = e1 - e0;
+        it.dt = dt;
+        it.Q = at(Q, e0, qe);
+        it.I = at(I, e0, qe);
+        it.traces = traces;
+        it.star = at(star_packed, e0, se);
+        it.Ap = reinterpret_cast<const double *>(at(Aplus, e0, ae));
+        it.Am = reinterpret_cast<const double *>(at(Aminus, e0, ae));
+        it.neigh = lts->neigh_rel + e0 * 4;
+        it.face_rot = reinterpret_cast<const uint8_t *>(at(face_rot, e0, 4));
+        it.first_block = 0;
+        it.nI = it.E + (c >= 0 ? lts->nghost[(size_t)c] : 0);
+        return it;
+    };
     const int64_t ticks = int64_t(1) << (C - 1);
     hipError_t h = hipSuccess;
 #define LTS_HIP(call)                                                      \
     do {                                                                   \
         if ((h = (call)) != hipSuccess) return hip_fail(h, "dg_lts_advance"); \
     } while (0)
-    const size_t tre = (size_t)4 * 9 * lts->plan->Bf * lts->elem;
-    auto item = [&](int c) {
-        const int64_t s0 = lts->start[(size_t)c];
-        DgItem it;
-        it.E = lts->start[(size_t)c + 1] - s0;
-        it.dt = std::ldexp(lts->dt0, c);
-        it.Q = atm(Q, s0, qe);
-        it.I = atm(lts->I, s0, qe);
-        it.traces = atm(lts->traces, s0, tre);
-        it.star = at(star_packed, s0, se);
-        it.Ap = reinterpret_cast<const double *>(at(Aplus, s0, ae * 8));
-        it.Am = reinterpret_cast<const double *>(at(Aminus, s0, ae * 8));
-        it.neigh = lts->neigh_rel + s0 * 4;
-        it.face_rot = reinterpret_cast<const uint8_t *>(at(face_rot, s0, 4));
-        it.first_block = 0;
-        return it;
-    };
     for (int cyc = 0; cyc < n_cycles; ++cyc) {
         for (int64_t tau = 0; tau < ticks; ++tau) {
             for (int c = 0; c < C; ++c) {
-                const int64_t s0 = lts->start[(size_t)c], n = lts->start[(size_t)c + 1] - s0;
-                if (n == 0 || tau % (int64_t(1) << c) != 0) continue;
-                const DgItem it = item(c);
-                LTS_HIP(t.step_predict(it, s));
-                const int64_t b0 = lts->bstart[(size_t)c], nb = s0 + n - b0;
-                if (lts->need_T[(size_t)c] && nb > 0)
-                    LTS_HIP(t.predictor(nb, it.dt, at(Q, b0, qe), at(star_packed, b0, se), atm(lts->T, b0, te), s));
+                const int64_t s0 = lts->start[(size_t)c], s1 = lts->start[(size_t)c + 1];
+                if (s1 == s0 || tau % (int64_t(1) << c) != 0) continue;
+                const double dtc = std::ldexp(lts->dt0, c);
+                LTS_HIP(t.step_predict(item(c, s0, s1, dtc, lts->I, at(lts->TR, lts->region[(size_t)c], te)), s));
+                const int64_t t0 = lts->tstart[(size_t)c];
+                if (t0 < s1)
+                    LTS_HIP(t.step_predict(item(-1, t0, s1, 0.5 * dtc, lts->IH, at(lts->TRH, t0, te)), s));
                 if (lts->nbuf[(size_t)c])
-                    LTS_HIP(dg_lts_buffer(fp64, lts->nbuf[(size_t)c], PB, lts->bids[(size_t)c], lts->I, lts->Buf,
-                                          tau % (int64_t(2) << c) == 0, s));
+                    LTS_HIP(dg_lts_tbuffer(fp64, lts->nbuf[(size_t)c], TB, lts->bids[(size_t)c], own_base(c),
+                                           lts->TRB, tau % (int64_t(2) << c) == 0, s));
             }
             for (int c = 0; c < C; ++c) {
-                const int64_t s0 = lts->start[(size_t)c], n = lts->start[(size_t)c + 1] - s0;
-                if (n == 0 || (tau + 1) % (int64_t(1) << c) != 0) continue;
-                // the receiver's step inside a step of the next cluster up:
-                // first half (a = 0) or second half (a = 1/2)
-                const int64_t a_ticks = tau + 1 - (int64_t(1) << c);
-                const double a = (a_ticks % (int64_t(2) << c)) ? 0.5 : 0.0, b = a + 0.5;
-                LtsWeights w = {};
-                const double dtu = std::ldexp(lts->dt0, c + 1);
-                for (int d = 0; d < N1; ++d)
-                    w.w[d] = dtu * (std::pow(b, d + 1) - std::pow(a, d + 1)) / (d + 1);
-                LTS_HIP(dg_lts_gather(fp64, lts->ng[(size_t)c], PB, N1, lts->gids[(size_t)c], lts->gkind[(size_t)c],
-                                      lts->T, lts->I, lts->Buf, lts->G, w, s));
-                LTS_HIP(t.step_correct(item(c), s));
-                const int64_t b0 = lts->bstart[(size_t)c], nb = s0 + n - b0;
-                if (nb > 0)
-                    LTS_HIP(t.neighbour_flux(nb, lts->E, lts->G, lts->neigh_for + b0 * 4,
-                                             reinterpret_cast<const uint8_t *>(at(face_rot, b0, 4)),
-                                             reinterpret_cast<const double *>(at(Aminus, b0, ae * 8)),
-                                             atm(Q, b0, qe), s));
+                const int64_t s0 = lts->start[(size_t)c], s1 = lts->start[(size_t)c + 1];
+                if (s1 == s0 || (tau + 1) % (int64_t(1) << c) != 0) continue;
+                if (lts->nghost[(size_t)c]) {
+                    // the receiver's step is the first or the second half of
+                    // a step of the next cluster up
+                    const int half = ((tau + 1 - (int64_t(1) << c)) % (int64_t(2) << c)) ? 1 : 0;
+                    const void *up = c + 1 < C ? own_base(c + 1) : lts->TR;
+                    LTS_HIP(dg_lts_ghosts(fp64, lts->nghost[(size_t)c], TB, lts->gids[(size_t)c],
+                                          lts->gkind[(size_t)c], half, up, lts->TRH, lts->TRB,
+                                          at(lts->TR, lts->region[(size_t)c] + (s1 - s0), te), s));
+                }
+                LTS_HIP(t.step_correct(item(c, s0, s1, 0.0, lts->I, at(lts->TR, lts->region[(size_t)c], te)), s));
             }
         }
     }

@@ -8,7 +8,8 @@ and their rate-2 cluster labels (inputs of local time stepping).  It is the one 
 both the oracle (test infrastructure) and the product path consume.
 """
 from .mesh import (CubeMesh, cube_mesh, random_materials, random_dofs, seed_for,
-                   dt_from_mesh, graded_cube_mesh, element_time_steps, rate2_clusters, permute_elements)
+                   dt_from_mesh, graded_cube_mesh, element_time_steps, rate2_clusters, permute_elements,
+                   layered_materials)
 
 __all__ = ["CubeMesh", "cube_mesh", "random_materials", "random_dofs", "seed_for", "dt_from_mesh",
-           "graded_cube_mesh", "element_time_steps", "rate2_clusters", "permute_elements"]
+           "graded_cube_mesh", "element_time_steps", "rate2_clusters", "permute_elements", "layered_materials"]

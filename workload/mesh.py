@@ -205,3 +205,15 @@ def permute_elements(mesh: CubeMesh, order: np.ndarray) -> CubeMesh:
     neigh = np.where(nb >= 0, inv[np.maximum(nb, 0)], -1).astype(np.int32)
     return CubeMesh(n=mesh.n, h=mesh.h, X=mesh.X[order], V=mesh.V[order], neigh=neigh,
                     nface=mesh.nface[order], orient=mesh.orient[order])
+
+
+def layered_materials(mesh: CubeMesh, seed: int, layer: float = 1.0 / 3.0, slowdown: float = 1.5):
+    """A slower layer over a halfspace: elements whose centroid has
+    z > 1 - layer take the layer material, the others the halfspace
+    material.  The halfspace material is one draw of random_materials; the
+    layer has the same density and both wave speeds divided by `slowdown`.
+    Returns (E, 3) float64 columns (rho, cp, cs)."""
+    half = random_materials(1, seed)[0]
+    lay = np.array([half[0], half[1] / slowdown, half[2] / slowdown])
+    top = mesh.X.mean(axis=1)[:, 2] > 1.0 - layer
+    return np.where(top[:, None], lay[None, :], half[None, :])
