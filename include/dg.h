@@ -316,6 +316,39 @@ int dg_lts_advance(dg_lts *lts, int n_cycles, void *Q, const void *star_packed, 
  * that uses it has finished). */
 int dg_lts_destroy(dg_lts *lts);
 
+/* ---- LinA: ADER-DG-SEM on cuboids ---------------------------------------- */
+
+/* The LinA scheme (Sec. 5.2): linear acoustics (quantities p, u, v, w) on a
+ * uniform periodic grid of cubes of edge h, tensor-product nodal basis on
+ * the `order` Gauss-Lobatto points per direction (degree order-1).  One time
+ * step is Eq. lina:derivative and Eq. lina:integration (the predictor and its
+ * time integral I), the weak derivatives Q* = Q + Kh I A* + ..., the side
+ * values of Eq. lin3d_evaluateSide and the side fluxes of Eq. lina3d_flux. */
+#define DG_LINA_MAX_ORDER_FP64 12
+#define DG_LINA_MAX_ORDER_FP32 16
+
+/* Number of doubles of a coefficient blob of the given order (-1 if outside
+ * [2, DG_LINA_MAX_ORDER_FP32]). */
+int64_t dg_lina_blob_size(int order);
+/* Fills the host FP64 coefficient blob: Kt [O][O] (minus the collocation
+ * derivative), Kh [O][O] (the weak derivative M^-1 S), the Gauss-Lobatto
+ * weights w [O] on [0, 1], the star matrices [3][4][4] (A/h, B/h, C/h of
+ * density rho0 and bulk modulus K0) and the upwind side flux solvers
+ * Ap, Am [6][4][4] (sides left, right, bottom, top, back, front; geometric
+ * factor -1/h folded in). */
+int dg_lina_coefficients(int order, double rho0, double K0, double h, double *out);
+/* n_steps time steps of dt.  Q [E][4][order][order][order] (x fastest),
+ * updated in place; sides [E][6][4][order][order] a work array (on return:
+ * the side values of the last step's time integral); coef the blob above
+ * copied to the device in the step's precision (double for DG_FP64, float
+ * for DG_FP32); neigh [E][6] the neighbour across each side (indices in
+ * [0, E); others drop that side's neighbour term).  Only the acoustic pattern of the
+ * star matrices is read (entries (0, 1+d) and (1+d, 0) of direction d).
+ * Orders up to DG_LINA_MAX_ORDER_FP64 / _FP32; device pointers, stream
+ * ordered. */
+int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, double dt, void *Q, void *sides,
+                 const double *coef, const int32_t *neigh, hipStream_t stream);
+
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller

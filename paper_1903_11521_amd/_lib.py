@@ -82,6 +82,10 @@ def _load():
         lib.dg_lts_clusters.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         lib.dg_lts_advance.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         lib.dg_lts_destroy.argtypes = [vp]
+        lib.dg_lina_blob_size.restype = i64
+        lib.dg_lina_blob_size.argtypes = [i32]
+        lib.dg_lina_coefficients.argtypes = [i32, dbl, dbl, dbl, dp]
+        lib.dg_lina_step.argtypes = [i32, i32, i64, i32, dbl, vp, vp, vp, vp, vp]
         _lib = lib
         return lib
 
@@ -519,6 +523,44 @@ class Lts:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# LinA: ADER-DG-SEM on cuboids (Sec. 5.2)
+# ---------------------------------------------------------------------------
+LINA_MAX_ORDER = {DG_FP64: 12, DG_FP32: 16}
+
+
+def lina_coefficients(order, rho0, K0, h):
+    """Host FP64 coefficient blob (dg_lina_coefficients) as a dict of arrays
+    plus the flat blob under "blob"."""
+    lib = _load()
+    n = lib.dg_lina_blob_size(int(order))
+    if n <= 0:
+        raise DGError("unsupported LinA order %d" % order)
+    buf = np.zeros(n)
+    _check(lib.dg_lina_coefficients(int(order), float(rho0), float(K0), float(h), _dptr(buf)))
+    O, out, o = int(order), {"blob": buf}, 0
+    for name, shape in (("Kt", (O, O)), ("Kh", (O, O)), ("w", (O,)), ("star", (3, 4, 4)), ("Ap", (6, 4, 4)),
+                        ("Am", (6, 4, 4))):
+        sz = int(np.prod(shape))
+        out[name] = buf[o:o + sz].reshape(shape)
+        o += sz
+    return out
+
+
+def lina_step(Q, sides, coef, neigh, dt, n_steps=1, stream=None):
+    """n_steps LinA steps (dg_lina_step) on device tensors: Q (E, 4, O, O, O)
+    float64 or float32, sides (E, 6, 4, O, O) of the same dtype, coef the
+    blob on the device in that dtype, neigh (E, 6) int32."""
+    torch = _torch()
+    E, O = int(Q.shape[0]), int(Q.shape[-1])
+    prec = DG_FP64 if Q.dtype == torch.float64 else DG_FP32
+    t = Plan._t
+    args = [t(None, Q, (E, 4, O, O, O), Q.dtype, "Q"), t(None, sides, (E, 6, 4, O, O), Q.dtype, "sides"),
+            t(None, coef, (int(_load().dg_lina_blob_size(O)),), Q.dtype, "coef"),
+            t(None, neigh, (E, 6), torch.int32, "neigh")]
+    _check(_load().dg_lina_step(prec, O, E, int(n_steps), float(dt), *args, Plan._stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -154,3 +154,28 @@ def test_lts_argument_errors():
     assert lib.dg_lts_advance(None, 1, *([None] * 7)) == -1
     lib.dg_plan_destroy(hb)
     lib.dg_plan_destroy(h)
+
+
+@pytest.mark.parametrize("order", [2, 3, 5, 8, 12, 16])
+def test_lina_coefficients_match_oracle(order):
+    """The product's LinA blob (Newton-iterated Gauss-Lobatto points, the
+    closed-form collocation derivative) against the oracle's (companion-
+    matrix roots, barycentric derivative)."""
+    import numpy as np
+    import paper_1903_11521_amd as dg
+    from oracle import lina
+    rho0, K0, h = 1.2, 1.4e5, 0.25
+    got = dg.lina_coefficients(order, rho0, K0, h)
+    m = lina.matrices(order - 1)
+    star, Ap, Am = lina.element_matrices(rho0, K0, h)
+    for name, ref in (("w", m["w"]), ("Kt", m["Kt"]), ("Kh", m["Kh"]), ("star", star), ("Ap", Ap), ("Am", Am)):
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(got[name] - ref)) <= 1e-12 * scale * order, name
+    lib = _lib()
+    assert lib.dg_lina_blob_size(1) == -1 and lib.dg_lina_blob_size(17) == -1
+    out = np.zeros(lib.dg_lina_blob_size(4))
+    assert lib.dg_lina_coefficients(4, -1.0, K0, h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == -1
+    assert lib.dg_lina_step(0, 13, 8, 1, 1e-3, *([None] * 5)) == -2      # FP64 order above the limit
+    assert lib.dg_lina_step(3, 4, 8, 1, 1e-3, *([None] * 5)) == -2       # split-BF16: not a LinA form
+    assert lib.dg_lina_step(0, 4, 8, 1, 1e-3, *([None] * 5)) == -1       # null pointers
+    assert lib.dg_lina_step(0, 4, 0, 1, 1e-3, *([None] * 5)) == 0        # empty grid
