@@ -44,11 +44,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness", "lts"],
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness", "lts", "lina"],
                     default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
                          "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh; "
-                         "madness: the separable contraction of Sec. 7; lts: local against global time stepping")
+                         "madness: the separable contraction of Sec. 7; lts: local against global time stepping; "
+                         "lina: the LinA ADER-DG-SEM scheme on cuboids (Sec. 5.2)")
     ap.add_argument("--grading", type=float, default=64.0, help="lts: cell-width ratio across the graded mesh")
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
@@ -351,6 +352,71 @@ def lts(args):
     print(json.dumps(out), flush=True)
 
 
+def lina(args):
+    """The LinA scheme (Sec. 5.2): linear acoustics on a periodic grid of
+    cubes with a tensor-product Gauss-Lobatto basis, at the paper's orders 8
+    (FP64 and FP32) and 16 (FP32), about 1 GiB of DOFs each (N(0,1) drawn on
+    the device), 10 steps timed with HIP events.  Useful flops per element
+    update count the derivative recursion and weak derivatives as line
+    contractions (12 O^4 per derivative or weak-derivative term set), the
+    time integral and the side fluxes (the acoustic flux solvers' non-zeros);
+    bytes count Q read and written, the sides written once and read twice
+    (own and neighbour), and the boundary nodes of Q updated by the flux."""
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1903)
+    rows = []
+    rho0, K0 = 1.2, 1.4e5
+    c = (K0 / rho0) ** 0.5
+    for dtype, name, order in ((torch.float64, "f64", 8), (torch.float32, "f32", 8), (torch.float32, "f32", 16)):
+        elem = 8 if dtype == torch.float64 else 4
+        n = max(2, int(round(((1 << 30) / (4 * order ** 3 * elem)) ** (1.0 / 3.0))))
+        E = n ** 3
+        h = 1.0 / n
+        dt = 0.3 * h / (c * (2 * order - 1))
+        idx = np.arange(E)
+        ix, iy, iz = idx % n, (idx // n) % n, idx // (n * n)
+        at = lambda a, b, cc: ((cc % n) * n + (b % n)) * n + (a % n)
+        neigh = np.stack([at(ix - 1, iy, iz), at(ix + 1, iy, iz), at(ix, iy - 1, iz), at(ix, iy + 1, iz),
+                          at(ix, iy, iz - 1), at(ix, iy, iz + 1)], axis=1).astype(np.int32)
+        coef = torch.from_numpy(dg.lina_coefficients(order, rho0, K0, h)["blob"]).to(dtype).to(dev)
+        Q = torch.randn((E, 4, order, order, order), generator=g, dtype=dtype, device=dev)
+        sides = torch.empty((E, 6, 4, order, order), dtype=dtype, device=dev)
+        nb = torch.from_numpy(neigh).to(dev)
+        dg.lina_step(Q, sides, coef, nb, dt, 1)
+        torch.cuda.synchronize()
+        steps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dg.lina_step(Q, sides, coef, nb, dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        el = e0.elapsed_time(e1) / 1e3 / steps
+        O3, O2, N = order ** 3, order ** 2, order - 1
+        flops = 12.0 * order ** 4 * (N + 1) + 8.0 * O3 * (N + 1) + 96.0 * O2
+        nbytes = (2 * 4 * O3 + 3 * 6 * 4 * O2 + 2 * 6 * 4 * O2) * elem
+        roof = pm.kernel_roofline(flops * E, nbytes * E, el, name)
+        rows.append({"dtype": name, "order": order, "elements": E, "ms_per_step": el * 1e3,
+                     "element_updates_per_s": E / el, "useful_gflops": flops * E / el / 1e9,
+                     "bound": roof["bound"], "frac": roof["frac"]})
+        log("lina %s order %d, %d elements: %.3f ms/step, %.1f M element-updates/s, %.0f GFLOP/s (%s, %.2f)"
+            % (name, order, E, el * 1e3, E / el / 1e6, flops * E / el / 1e9, roof["bound"], roof["frac"]))
+        del Q, sides, coef
+    best = max(r["useful_gflops"] for r in rows if r["dtype"] == "f64")
+    out = {"metric": "useful GFLOP/s", "value": best, "unit": "GFLOP/s", "n_gpus": 1, "steps": 10, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 and f32", "data": "synthetic",
+           "config": {"workload": "LinA ADER-DG-SEM (Sec. 5.2): linear acoustics on a periodic grid of cubes, "
+                                  "Gauss-Lobatto tensor basis of order 8 (FP64, FP32) and 16 (FP32), about 1 GiB "
+                                  "of DOFs"},
+           "lina": rows}
+    print(json.dumps(out), flush=True)
+
+
 def madness(args):
     """The separable contraction of Sec. 7 (Eq. stock_mra): batches of random
     p x p x p tensors (1 GiB of inputs, resident in HBM) and operator pairs of
@@ -479,6 +545,8 @@ def main():
         return madness(args)
     if args.workload == "lts":
         return lts(args)
+    if args.workload == "lina":
+        return lina(args)
     if args.workload == "serving":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"
