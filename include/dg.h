@@ -119,6 +119,17 @@ int dg_reference_matrices(int degree, double *out);
  * neigh [E][4].  Writes star [E][3][9][9] (A*^d = sum_j dxi_d/dx_j A^(j),
  * Sec. 5.1.1), Aplus and Aminus [E][4][9][9] (exact Godunov flux between the
  * element's and the neighbour's isotropic materials).  Host pointers. */
+/* Viscoelastic element data (three mechanisms; 27 quantities: the 9
+ * elastic ones, then 6 memory variables per mechanism).  omega [3] the
+ * mechanisms' relaxation frequencies, Ylam, Ymu [E][3] their coefficients;
+ * star [E][3][27][9] and Aplus, Aminus [E][4][27][9]: the rows of all 27
+ * quantities over the 9 elastic columns (the only ones the operators read).
+ * Memory rows: the stress rows of the Jacobians with (lambda, mu) replaced by
+ * (omega_l Ylam_l, omega_l Ymu_l); on faces they take the elastic Godunov
+ * state.  Host arrays; returns 0, or -1 for a null pointer or E < 0. */
+int dg_visco_element_data_host(int64_t E, const double *X, const double *materials, const double *omega,
+                               const double *Ylam, const double *Ymu, const int32_t *neigh, double *star,
+                               double *Aplus, double *Aminus);
 int dg_element_data_host(int64_t E, const double *X, const double *materials, const int32_t *neigh,
                          double *star, double *Aplus, double *Aminus);
 
@@ -315,6 +326,25 @@ int dg_lts_advance(dg_lts *lts, int n_cycles, void *Q, const void *star_packed, 
 /* Frees the handle and its device memory (after the caller's stream work
  * that uses it has finished). */
 int dg_lts_destroy(dg_lts *lts);
+
+/* ---- viscoelastic elements ------------------------------------------------ */
+
+/* n_steps global steps of the viscoelastic scheme (27 quantities: the 9
+ * elastic ones, then 3 mechanisms x 6 memory variables; Sec. 5.1 names the
+ * rheology): the ADER step of Eqs. seissol:derivative, seissol:timeint,
+ * seissol:correction_local and seissol:correction_neigh with 27 rows, plus
+ * the source terms D^d E^T in the derivative recursion and I E^T in the
+ * update (E: stress rows -sum_l theta_l, memory rows -omega_l theta_l), and
+ * no derivative staircase.  FP64 device arrays: Q, I [E][27][B] (Q updated
+ * in place, I work), traces [E][4][9][Bf] work (the elastic face traces of
+ * I), star [E][3][27][9], Aplus, Aminus [E][4][27][9] (from
+ * dg_visco_element_data_host), ref the blob of dg_reference_matrices for
+ * the degree copied to the device, neigh [E][4] (indices outside [0, E): no
+ * neighbour), face_rot [E][4] = j | h << 2; omega [3] a HOST array of the
+ * relaxation frequencies.  Degrees 2..6. */
+int dg_visco_step(int degree, int64_t E, double dt, int n_steps, double *Q, double *I, double *traces,
+                  const double *star, const double *Aplus, const double *Aminus, const double *omega,
+                  const double *ref, const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
 
 /* ---- LinA: ADER-DG-SEM on cuboids ---------------------------------------- */
 

@@ -52,6 +52,8 @@ def _load():
         lib.dg_reference_blob_size.argtypes = [i32]
         lib.dg_reference_matrices.argtypes = [i32, dp]
         lib.dg_element_data_host.argtypes = [i64, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp, dp]
+        lib.dg_visco_element_data_host.argtypes = [i64, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
+                                                   dp]
         lib.dg_plan_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
         lib.dg_plan_destroy.argtypes = [vp]
         lib.dg_plan_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -86,6 +88,7 @@ def _load():
         lib.dg_lina_blob_size.argtypes = [i32]
         lib.dg_lina_coefficients.argtypes = [i32, dbl, dbl, dbl, dp]
         lib.dg_lina_step.argtypes = [i32, i32, i64, i32, dbl, vp, vp, vp, vp, vp]
+        lib.dg_visco_step.argtypes = [i32, i64, dbl, i32, vp, vp, vp, vp, vp, vp, dp, vp, vp, vp, vp]
         _lib = lib
         return lib
 
@@ -108,6 +111,18 @@ def _dptr(a):
 # ---------------------------------------------------------------------------
 # host helpers
 # ---------------------------------------------------------------------------
+def reference_blob(degree: int) -> np.ndarray:
+    """The packed reference-matrix blob of dg_reference_matrices (FP64), as
+    the step kernels take it on the device."""
+    lib = _load()
+    n = lib.dg_reference_blob_size(degree)
+    if n <= 0:
+        raise DGError("unsupported degree %d" % degree)
+    buf = np.zeros(n)
+    _check(lib.dg_reference_matrices(degree, _dptr(buf)))
+    return buf
+
+
 def reference_matrices(degree: int) -> dict:
     lib = _load()
     n = lib.dg_reference_blob_size(degree)
@@ -139,6 +154,31 @@ def element_data(X, materials, neigh):
     Am = np.empty((E, 4, 9, 9))
     _check(lib.dg_element_data_host(E, _dptr(X), _dptr(mats), nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                     _dptr(star), _dptr(Ap), _dptr(Am)))
+    return star, Ap, Am
+
+
+def visco_element_data(X, materials, omega, Ylam, Ymu, neigh):
+    """Viscoelastic star matrices (E,3,27,9) and flux solvers A+, A- (E,4,27,9)
+    on the host (27 rows: elastic, then 3 mechanisms x 6 memory variables;
+    the 9 elastic columns)."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    mats = np.ascontiguousarray(materials, dtype=np.float64)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    yl = np.ascontiguousarray(Ylam, dtype=np.float64)
+    ym = np.ascontiguousarray(Ymu, dtype=np.float64)
+    nb = np.ascontiguousarray(neigh, dtype=np.int32)
+    E = X.shape[0]
+    if (X.shape != (E, 4, 3) or mats.shape != (E, 3) or om.shape != (3,) or yl.shape != (E, 3)
+            or ym.shape != (E, 3) or nb.shape != (E, 4)):
+        raise ValueError("visco_element_data: expected X (E,4,3), materials (E,3), omega (3,), Ylam, Ymu (E,3), "
+                         "neigh (E,4)")
+    star = np.empty((E, 3, 27, 9))
+    Ap = np.empty((E, 4, 27, 9))
+    Am = np.empty((E, 4, 27, 9))
+    _check(lib.dg_visco_element_data_host(E, _dptr(X), _dptr(mats), _dptr(om), _dptr(yl), _dptr(ym),
+                                          nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(star),
+                                          _dptr(Ap), _dptr(Am)))
     return star, Ap, Am
 
 
@@ -523,6 +563,30 @@ class Lts:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# viscoelastic elements (27 quantities)
+# ---------------------------------------------------------------------------
+def visco_step(degree, Q, I, traces, star, Aplus, Aminus, omega, ref, neigh, face_rot, dt, n_steps=1, stream=None):
+    """n_steps viscoelastic steps (dg_visco_step) on FP64 device tensors:
+    Q, I (E, 27, B); traces (E, 4, 9, Bf); star (E, 3, 27, 9); Aplus, Aminus
+    (E, 4, 27, 9); ref the dg_reference_matrices blob of the degree on the
+    device; neigh (E, 4) int32; face_rot (E, 4) uint8; omega 3 floats."""
+    torch = _torch()
+    E = int(Q.shape[0])
+    B, Bf = comb(degree + 3, 3), comb(degree + 2, 2)
+    t, f64 = Plan._t, torch.float64
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    if om.shape != (3,):
+        raise ValueError("omega must hold 3 values")
+    args = [t(None, Q, (E, 27, B), f64, "Q"), t(None, I, (E, 27, B), f64, "I"),
+            t(None, traces, (E, 4, 9, Bf), f64, "traces"), t(None, star, (E, 3, 27, 9), f64, "star"),
+            t(None, Aplus, (E, 4, 27, 9), f64, "Aplus"), t(None, Aminus, (E, 4, 27, 9), f64, "Aminus")]
+    refp = t(None, ref, (int(_load().dg_reference_blob_size(degree)),), f64, "ref")
+    _check(_load().dg_visco_step(int(degree), E, float(dt), int(n_steps), *args, _dptr(om), refp,
+                                 t(None, neigh, (E, 4), torch.int32, "neigh"),
+                                 t(None, face_rot, (E, 4), torch.uint8, "face_rot"), Plan._stream(stream)))
 
 
 # ---------------------------------------------------------------------------

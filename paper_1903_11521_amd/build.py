@@ -115,10 +115,11 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
         deps[o] = c("mfma_launch.hip", "mfma_kernels.hip", "dg_common.h", "dg_tables.h") + gen_mfma
         objs.append(o)
     for src in ("dg_api.cpp", "refmat.cpp", "elements.cpp", "dg_noalloc.hip", "mra_kernels.hip", "lts.cpp",
-                "lts_kernels.hip", "lina.cpp", "lina_kernels.hip"):
+                "lts_kernels.hip", "lina.cpp", "lina_kernels.hip", "visco.cpp", "visco_kernels.hip"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o").replace(".hip", ".o"))
         cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
-        deps[o] = c(src, "dg_internal.h", "dg_tables.h", "refmat.h", "lts_internal.h", "lina_internal.h") + pub
+        deps[o] = c(src, "dg_internal.h", "dg_tables.h", "refmat.h", "lts_internal.h", "lina_internal.h",
+                    "visco_internal.h", "dg_common.h") + pub
         objs.append(o)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:

@@ -179,3 +179,25 @@ def test_lina_coefficients_match_oracle(order):
     assert lib.dg_lina_step(3, 4, 8, 1, 1e-3, *([None] * 5)) == -2       # split-BF16: not a LinA form
     assert lib.dg_lina_step(0, 4, 8, 1, 1e-3, *([None] * 5)) == -1       # null pointers
     assert lib.dg_lina_step(0, 4, 0, 1, 1e-3, *([None] * 5)) == 0        # empty grid
+
+
+def test_visco_element_data_matches_oracle():
+    """The product's viscoelastic star and flux rows (impedance form of the
+    Godunov state) against the oracle's (eigenvector projector)."""
+    import numpy as np
+    import paper_1903_11521_amd as dg
+    from oracle import viscoelastic as ve
+    from workload import cube_mesh, random_materials, seed_for
+    mesh = cube_mesh(3, seed_for(7), relabel=True)
+    mats = random_materials(mesh.E, seed_for(7))
+    omega = np.array([0.7, 3.0, 9.0])
+    Ylam, Ymu = ve.memory_parameters(mats, omega, [0.02, 0.01, 0.04], [0.03, 0.015, 0.005])
+    nb = mesh.neigh.copy()
+    nb[0, 2] = -1
+    star, Ap, Am = dg.visco_element_data(mesh.X, mats, omega, Ylam, Ymu, nb)
+    ostar = ve.star_matrices(mesh.X, mats, omega, Ylam, Ymu)
+    oAp, oAm = ve.flux_matrices(mesh.X, mats, omega, Ylam, Ymu, nb)
+    assert np.all(ostar[..., 9:] == 0) and np.all(oAp[..., 9:] == 0) and np.all(oAm[..., 9:] == 0)
+    for got, ref in ((star, ostar[..., :9]), (Ap, oAp[..., :9]), (Am, oAm[..., :9])):
+        assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert np.all(Am[0, 2] == 0)

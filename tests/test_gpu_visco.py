@@ -1,0 +1,92 @@
+"""GPU parity of the viscoelastic step (dg_visco_step, 27 quantities)
+through the C ABI against the viscoelastic oracle (oracle/viscoelastic.py).
+
+The GPU runs on the product's element data (dg_visco_element_data_host) and
+reference matrices, the oracle on its own.  Relaxation frequencies are
+chosen so that omega dt is 0.02-0.3 (the source terms matter); memory
+coefficients as the workload draws them.  Bar: FP64 1e-12 on the step
+increment, per quantity and per element (dgtest), over all 27 quantities.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from dgtest import assert_close
+from oracle import refmat
+from oracle import viscoelastic as ve
+from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _case(N, n, seed, relabel=True):
+    mesh = cube_mesh(n, seed_for(seed), relabel=relabel)
+    mats = random_materials(mesh.E, seed_for(seed))
+    dt = dt_from_mesh(mesh, mats)
+    omega = np.array([0.02, 0.1, 0.3]) / dt
+    Ylam, Ymu = ve.memory_parameters(mats, omega, [0.02, 0.01, 0.04], [0.03, 0.015, 0.005])
+    B = refmat.refmats(N).B
+    Q = random_dofs(mesh.E, 27, B, seed)
+    return mesh, mats, dt, omega, Ylam, Ymu, Q
+
+
+def _gpu(N, mesh, mats, dt, omega, Ylam, Ymu, Q, steps, neigh=None):
+    import paper_1903_11521_amd as dg
+    nb = mesh.neigh if neigh is None else neigh
+    star, Ap, Am = dg.visco_element_data(mesh.X, mats, omega, Ylam, Ymu, nb)
+    ref = _dev(dg.reference_blob(N))
+    E = mesh.E
+    Qg = _dev(Q)
+    I = torch.empty_like(Qg)
+    Bf = refmat.refmats(N).Bf
+    tr = torch.empty((E, 4, 9, Bf), dtype=torch.float64, device="cuda:0")
+    dg.visco_step(N, Qg, I, tr, _dev(star), _dev(Ap), _dev(Am), omega, ref, _dev(nb.astype(np.int32)), _dev(mesh.face_rot), dt,
+                  steps)
+    torch.cuda.synchronize()
+    return Qg.cpu().numpy()
+
+
+def _oracle(N, mesh, mats, dt, omega, Ylam, Ymu, Q, steps, neigh=None):
+    nb = mesh.neigh if neigh is None else neigh
+    rm = refmat.refmats(N)
+    star = ve.star_matrices(mesh.X, mats, omega, Ylam, Ymu)
+    Ap, Am = ve.flux_matrices(mesh.X, mats, omega, Ylam, Ymu, nb)
+    Es = ve.source_matrix(omega)
+    for _ in range(steps):
+        Q = ve.step(rm, dt, Q, star, Ap, Am, Es, nb, mesh.nface, mesh.orient)
+    return Q
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_visco_step_matches_oracle(N):
+    _say(f"test_visco_step_matches_oracle N={N}")
+    case = _case(N, 3, 20 + N)
+    got = _gpu(N, *case, 1)
+    ref = _oracle(N, *case, 1)
+    Q = case[-1]
+    assert_close(got - Q, ref - Q, 1e-12, "viscoelastic step increment")
+
+
+def test_visco_two_steps_and_missing_neighbours():
+    _say("test_visco_two_steps_and_missing_neighbours")
+    N = 4
+    case = _case(N, 3, 31)
+    mesh = case[0]
+    nb = mesh.neigh.copy()
+    nb[0, 1] = -1
+    nb[7, 3] = -1
+    got = _gpu(N, *case, 2, neigh=nb)
+    ref = _oracle(N, *case, 2, neigh=nb)
+    Q = case[-1]
+    assert_close(got - Q, ref - Q, 1e-12, "two-step increment")
