@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness", "lts", "lina"],
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "fused", "madness", "lts", "lina",
+                                                "visco"],
                     default="single",
                     help="single: one degree-N mesh; batched: 32 independent meshes of mixed degree; "
                          "serving: Poisson arrivals of ensemble requests; fused: 16 simulations per mesh; "
@@ -417,6 +418,79 @@ def lina(args):
     print(json.dumps(out), flush=True)
 
 
+def visco(args):
+    """Viscoelastic elements (27 quantities, three mechanisms) on the
+    n x n x n cube-split mesh with random materials, degrees 3 and the
+    --degree one, DOFs N(0,1) drawn on the device, relaxation frequencies
+    with omega dt = 0.02, 0.1, 0.3, 10 steps timed with HIP events on the
+    launch stream.  Useful flops per element update count the executed
+    contractions over the 9 elastic columns the Jacobians read (predictor
+    recursion, traces, volume, the four faces' f^h, flux-solver and lift
+    products) and the source terms; bytes count Q (read twice, written
+    once), the time integral (written, read), the traces (written, read own
+    and neighbour), the star matrices (read twice) and the flux solvers."""
+    from math import comb
+
+    import torch
+
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd import perfmodel as pm
+    from workload import cube_mesh, dt_from_mesh, random_materials, seed_for
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1903)
+    mesh = cube_mesh(args.n, seed_for(0), relabel=True)
+    mats = random_materials(mesh.E, seed_for(0))
+    dt = dt_from_mesh(mesh, mats)
+    omega = np.array([0.02, 0.1, 0.3]) / dt
+    mu = mats[:, 0] * mats[:, 2] ** 2                    # rho cs^2
+    lam = mats[:, 0] * mats[:, 1] ** 2 - 2.0 * mu        # rho cp^2 - 2 mu
+    Ylam = lam[:, None] * np.array([0.02, 0.01, 0.04])[None, :]
+    Ymu = mu[:, None] * np.array([0.03, 0.015, 0.005])[None, :]
+    star, Ap, Am = dg.visco_element_data(mesh.X, mats, omega, Ylam, Ymu, mesh.neigh)
+    E = mesh.E
+    star_d, Ap_d, Am_d = (torch.from_numpy(a).to(dev) for a in (star, Ap, Am))
+    del star, Ap, Am
+    nb = torch.from_numpy(np.ascontiguousarray(mesh.neigh, dtype=np.int32)).to(dev)
+    fr = torch.from_numpy(mesh.face_rot).to(dev)
+    rows = []
+    for N in sorted({3, args.degree}):
+        B, Bf = comb(N + 3, 3), comb(N + 2, 2)
+        ref = torch.from_numpy(dg.reference_blob(N)).to(dev)
+        Q = torch.randn((E, 27, B), generator=g, dtype=torch.float64, device=dev)
+        I = torch.empty_like(Q)
+        tr = torch.empty((E, 4, 9, Bf), dtype=torch.float64, device=dev)
+        dg.visco_step(N, Q, I, tr, star_d, Ap_d, Am_d, omega, ref, nb, fr, dt, 1)
+        torch.cuda.synchronize()
+        steps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dg.visco_step(N, Q, I, tr, star_d, Ap_d, Am_d, omega, ref, nb, fr, dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        el = e0.elapsed_time(e1) / 1e3 / steps
+        star_fl = 3 * (2 * B * B * 9 + 2 * B * 9 * 27)
+        flops = (N + 1) * star_fl + 4 * 2 * B * Bf * 9 + 4 * (2 * Bf * Bf * 9 + 4 * Bf * 27 * 9 + 2 * B * Bf * 27) \
+            + (N + 1) * (36 + 2 * 27) * B
+        nbytes = 8 * (3 * 27 * B + 2 * 27 * B + 3 * 4 * 9 * Bf + 2 * 3 * 27 * 9 + 2 * 4 * 27 * 9) + 4 * 5
+        roof = pm.kernel_roofline(flops * E, nbytes * E, el, "f64")
+        rows.append({"degree": N, "elements": E, "ms_per_step": el * 1e3, "element_updates_per_s": E / el,
+                     "useful_gflops": flops * E / el / 1e9, "flops_per_element": flops,
+                     "bytes_per_element": nbytes, "bound": roof["bound"], "frac": roof["frac"]})
+        log("visco degree %d, %d elements: %.3f ms/step, %.2f M element-updates/s, %.0f GFLOP/s (%s, %.3f)"
+            % (N, E, el * 1e3, E / el / 1e6, flops * E / el / 1e9, roof["bound"], roof["frac"]))
+        del Q, I, tr, ref
+    top = rows[-1]
+    out = {"metric": "element updates per second", "value": top["element_updates_per_s"], "unit": "1/s",
+           "n_gpus": 1, "steps": 10, "warmup": 1, "ms_per_step": top["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "viscoelastic ADER-DG (27 quantities, 3 mechanisms), degree %d, %dx%dx%dx6 = "
+                                  "%d-element jittered periodic cube-split mesh, random materials"
+                                  % (top["degree"], args.n, args.n, args.n, E)},
+           "visco": rows}
+    print(json.dumps(out), flush=True)
+
+
 def madness(args):
     """The separable contraction of Sec. 7 (Eq. stock_mra): batches of random
     p x p x p tensors (1 GiB of inputs, resident in HBM) and operator pairs of
@@ -547,6 +621,8 @@ def main():
         return lts(args)
     if args.workload == "lina":
         return lina(args)
+    if args.workload == "visco":
+        return visco(args)
     if args.workload == "serving":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"

@@ -1,20 +1,34 @@
 // Viscoelastic ADER-DG step (27 quantities: the 9 elastic ones, then 3
-// mechanisms x 6 memory variables; Sec. 5.1 names the rheology).  Per
-// element, FP64, one workgroup of 256 threads:
-//   k_visco_predict:  D^{d+1} = sum_dir (Kt_dir D_el^T) S_dir^T + D^d E^T
+// mechanisms x 6 memory variables; Sec. 5.1 names the rheology), FP64.
+//   k_visco_predict:  D^{d+1} = sum_dir (Kt_dir D_el) S_dir^T + D^d E^T
 //                     (Eq. seissol:derivative with the source term; D_el the
 //                     9 elastic columns, the only ones the star matrices S
 //                     read), I = sum_d dt^{d+1}/(d+1)! D^d (Eq. seissol:timeint),
 //                     face traces R_s^T I_el;
-//   k_visco_correct:  Q += sum_dir (Kh_dir I_el^T) S_dir^T
+//   k_visco_correct:  Q += sum_dir (Kh_dir I_el) S_dir^T
 //                          + sum_s Rh_s [A+_s (R_s^T I_el) + A-_s f^h (R_j^T I_el[nu])]
 //                          + I E^T
 //                     (Eqs. seissol:correction_local and seissol:correction_neigh
 //                     with one lift per face).
 // E: stress rows gain -sum_l theta_l, memory rows -omega_l theta_l.
-// The element's arrays live in LDS with the basis index as the row
-// ([B][27]); every reference-matrix product is a small GEMM on the matrix
-// cores (v_mfma_f64_16x16x4f64) with the reference matrix staged in LDS.
+//
+// Persistent workgroups of 256 threads walk the elements of a work list (one
+// mesh, or the viscoelastic meshes of one degree in a batch).  Every product
+// is a chain of v_mfma_f64_16x16x4f64 tiles.  Per element:
+//  * predictor: the derivative D^d sits in LDS as [B][27] (basis index as the
+//    row); per order one phase computes G_dir = Kt_dir D_el for the three
+//    directions and a second phase D^{d+1} = [G_1 G_2 G_3] [S_1 S_2 S_3]^T
+//    plus the source, with the time integral accumulated in the registers of
+//    the wave that owns each 16 x 16 output tile: two barriers per order;
+//  * corrector: phase A computes G_dir = Kh_dir I_el and X_s = f^h x_nbr,
+//    phase B the volume product into registers and F_s = [x_own X_s]
+//    [A+_s A-_s]^T, phase C adds sum_s Rh_s F_s (one K = 4 Bf product).
+// The hierarchical basis makes Kt_dir zero unless the column's degree exceeds
+// the row's, and Kh_dir zero unless it is below: the rows of Kt of degree N
+// and the columns of Kh of degree N are dropped, and each tile skips the
+// k-steps of its zero block.  These reference matrices stay resident in LDS
+// for the workgroup's lifetime where two workgroups per CU still fit;
+// otherwise the tiles read them from the (L2-resident) blob.
 // Layouts: Q, I [E][27][B]; star [E][3][27][9]; Aplus, Aminus [E][4][27][9];
 // traces [E][4][9][Bf]; the reference blob as dg_reference_matrices writes it.
 #include <hip/hip_runtime.h>
@@ -30,245 +44,436 @@ using dgk::nb3;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NQ = 27, NE = 9, THREADS = 256, WAVES = THREADS / 64;
+constexpr int LDS_TWO_PER_CU = 80 * 1024;
 
-// C (+)= A B (M x K times K x N), operands at A[i ar + k ac], B[k br + j bc],
-// C[i cr + j cc].  16 x 16 tiles dealt to the waves; MFMA lane layout: A[i][k]
-// in lane 16k + i, B[k][j] in lane 16k + j, output register r of lane l is
-// row l/16 + 4r, column l%16.  The caller synchronises around it.
-__device__ void gemm(int M, int N, int K, const double *A, int ar, int ac, const double *B, int br, int bc,
-                     double *C, int cr, int cc, bool acc)
+// polynomial degree of basis function r (the basis is ordered by degree)
+__host__ __device__ constexpr int deg_of(int r)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int MT = (M + 15) >> 4, NT = (N + 15) >> 4, KS = (K + 3) >> 2;
-    for (int t = wave; t < MT * NT; t += WAVES) {
-        const int mt = t / NT, nt = t - mt * NT;
-        const int i = 16 * mt + li, j = 16 * nt + li;
-        d4 c = {0.0, 0.0, 0.0, 0.0};
-        for (int s = 0; s < KS; ++s) {
-            const int k = 4 * s + lk;
-            const double a = (i < M && k < K) ? A[i * ar + k * ac] : 0.0;
-            const double b = (k < K && j < N) ? B[k * br + j * bc] : 0.0;
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * mt + lk + 4 * r;
-            if (row < M && j < N) {
-                double *o = C + row * cr + j * cc;
-                *o = acc ? *o + c[r] : c[r];
-            }
-        }
-    }
+    int d = 0;
+    while (nb3(d) <= r) ++d;
+    return d;
 }
 
-__device__ __forceinline__ void copy(double *dst, const double *__restrict__ src, int n)
+template <int N>
+struct Dim {
+    static constexpr int B = nb3(N), Bf = nb2(N), B1 = nb3(N - 1);
+    // odd row strides of the LDS matrices read 16 rows at a time (no bank conflicts)
+    static constexpr int BP = B | 1, B1P = B1 | 1, BfP = Bf | 1, WP = 19;
+    static constexpr int MT = (B + 15) / 16, MT1 = (B1 + 15) / 16, MTf = (Bf + 15) / 16;
+    static constexpr int OT = 2 * MT;                      // 16 x 16 tiles of a [B][27] array
+    static constexpr int TPW = (OT + WAVES - 1) / WAVES;   // of them owned per wave
+    static constexpr int QPT = (NQ * B + THREADS - 1) / THREADS;
+    // predictor LDS (doubles): D, Dn [B][27], G [B1][27]; Kt rows of degree < N [3][B1][BP] if resident
+    static constexpr int P_EL = 2 * B * NQ + B1 * NQ, P_KT = 3 * B1 * BP;
+    static constexpr bool P_RES = 8 * (P_EL + P_KT) <= LDS_TWO_PER_CU;
+    static constexpr int P_LDS = P_EL + (P_RES ? P_KT : 0);
+    // corrector LDS: f [3][Bf][BfP], I_el [B][9], G [B][27], X [4 Bf][9], F [4 Bf][27],
+    // own traces [4][9][Bf], neighbour traces [4][9][BfP], [A+ A-] [4][27][WP];
+    // Kh columns of degree < N [3][B][B1P] if resident
+    static constexpr int C_EL = 3 * Bf * BfP + B * NE + B * NQ + 4 * Bf * NE + 4 * Bf * NQ + 4 * NE * Bf +
+                                4 * NE * BfP + 4 * NQ * WP;
+    static constexpr int C_KH = 3 * B * B1P;
+    static constexpr bool C_RES = 8 * (C_EL + C_KH) <= LDS_TWO_PER_CU;
+    static constexpr int C_LDS = C_EL + (C_RES ? C_KH : 0);
+};
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 {
-    for (int i = threadIdx.x; i < n; i += THREADS) dst[i] = src[i];
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // (E x)[p] for the structured source matrix, x a row of 27 values
-__device__ __forceinline__ double source(const double *x, int p, const double *omega)
+__device__ __forceinline__ double source(const double *x, int p, double w0, double w1, double w2)
 {
     if (p < 6) return -(x[9 + p] + x[15 + p] + x[21 + p]);
     if (p < 9) return 0.0;
-    return -omega[(p - 9) / 6] * x[p];
+    return -(p < 15 ? w0 : (p < 21 ? w1 : w2)) * x[p];
 }
 
-struct Ref {
-    const double *Kh, *Kt, *R, *Rh, *f;
-};
-
-template <int N>
-__device__ __forceinline__ Ref ref_of(const double *blob)
+// the star matrices as the B operand [S_1 S_2 S_3]^T: row k = 9 dir + q,
+// column p; the 7 k-steps of column `col` for lane row lk
+__device__ __forceinline__ void star_b(const double *Se, int col, int lk, double (&sb)[7])
 {
-    constexpr int B = nb3(N), Bf = nb2(N);
-    Ref r;
-    r.Kh = blob;
-    r.Kt = blob + 3 * B * B;
-    r.R = blob + 6 * B * B;
-    r.Rh = r.R + 4 * B * Bf;
-    r.f = r.Rh + 4 * B * Bf;
-    return r;
-}
-
-template <int N>
-constexpr int predict_lds() { return 3 * nb3(N) * NQ + nb3(N) * nb3(N) + NE * nb3(N) + 3 * NQ * NE + NE * nb2(N); }
-template <int N>
-constexpr int correct_lds() { return 2 * nb3(N) * NQ + nb3(N) * nb3(N) + NE * nb3(N) + 3 * NQ * NE + 3 * NE * nb2(N) + NQ * nb2(N); }
-
-template <int N>
-__global__ void __launch_bounds__(THREADS)
-k_visco_predict(double dt, const double *__restrict__ Q, const double *__restrict__ star, VOmega om,
-                const double *__restrict__ blob, double *__restrict__ Iout, double *__restrict__ traces)
-{
-    constexpr int B = nb3(N), Bf = nb2(N);
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *D = reinterpret_cast<double *>(lds_raw), *Dn = D + B * NQ, *Is = Dn + B * NQ, *Mb = Is + B * NQ,
-           *G = Mb + B * B, *S = G + NE * B, *tr = S + 3 * NQ * NE;
-    const Ref rf = ref_of<N>(blob);
-    const int64_t e = blockIdx.x;
-    const double *Qe = Q + e * NQ * B;
-    for (int i = threadIdx.x; i < NQ * B; i += THREADS) {
-        const int p = i / B, k = i - p * B;
-        const double v = Qe[i];
-        D[k * NQ + p] = v;
-        Is[k * NQ + p] = dt * v;
-    }
-    copy(S, star + e * 3 * NQ * NE, 3 * NQ * NE);
-    double c = dt;
-    for (int d = 0; d < N; ++d) {
-        for (int dir = 0; dir < 3; ++dir) {
-            __syncthreads();
-            copy(Mb, rf.Kt + dir * B * B, B * B);
-            __syncthreads();
-            gemm(B, NE, B, Mb, B, 1, D, NQ, 1, G, NE, 1, false);                      // G = Kt D_el^T
-            __syncthreads();
-            gemm(B, NQ, NE, G, NE, 1, S + dir * NQ * NE, 1, NE, Dn, NQ, 1, dir > 0);  // Dn (+)= G S^T
-        }
-        __syncthreads();
-        c *= dt / (d + 2);
-        for (int i = threadIdx.x; i < NQ * B; i += THREADS) {
-            const int k = i / NQ, p = i - k * NQ;
-            const double v = Dn[i] + source(D + k * NQ, p, om.w);
-            Dn[i] = v;
-            Is[i] += c * v;
-        }
-        __syncthreads();
-        double *t = D;
-        D = Dn;
-        Dn = t;
-    }
-    double *Ie = Iout + e * NQ * B;
-    for (int i = threadIdx.x; i < NQ * B; i += THREADS) {
-        const int p = i / B, k = i - p * B;
-        Ie[i] = Is[k * NQ + p];
-    }
-    for (int s = 0; s < 4; ++s) {
-        __syncthreads();
-        copy(Mb, rf.R + s * B * Bf, B * Bf);
-        __syncthreads();
-        gemm(Bf, NE, B, Mb, 1, Bf, Is, NQ, 1, tr, NE, 1, false);                     // tr = R_s^T I_el
-        __syncthreads();
-        double *te = traces + (e * 4 + s) * NE * Bf;
-        for (int i = threadIdx.x; i < NE * Bf; i += THREADS) {
-            const int q = i / Bf, m = i - q * Bf;
-            te[i] = tr[m * NE + q];
-        }
-    }
-}
-
-template <int N>
-__global__ void __launch_bounds__(THREADS)
-k_visco_correct(int64_t E, const double *__restrict__ I, const double *__restrict__ traces,
-                const double *__restrict__ star, const double *__restrict__ Ap, const double *__restrict__ Am,
-                const int32_t *__restrict__ neigh, const uint8_t *__restrict__ face_rot, VOmega om,
-                const double *__restrict__ blob, double *__restrict__ Q)
-{
-    constexpr int B = nb3(N), Bf = nb2(N);
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *Is = reinterpret_cast<double *>(lds_raw), *acc = Is + B * NQ, *Mb = acc + B * NQ, *G = Mb + B * B,
-           *S = G + NE * B, *trO = S + 3 * NQ * NE, *trN = trO + NE * Bf, *X = trN + NE * Bf, *F = X + NE * Bf;
-    const Ref rf = ref_of<N>(blob);
-    const int64_t e = blockIdx.x;
-    const double *Ie = I + e * NQ * B;
-    for (int i = threadIdx.x; i < NQ * B; i += THREADS) {
-        const int p = i / B, k = i - p * B;
-        Is[k * NQ + p] = Ie[i];
-    }
-    copy(S, star + e * 3 * NQ * NE, 3 * NQ * NE);
-    // volume
-    for (int dir = 0; dir < 3; ++dir) {
-        __syncthreads();
-        copy(Mb, rf.Kh + dir * B * B, B * B);
-        __syncthreads();
-        gemm(B, NE, B, Mb, B, 1, Is, NQ, 1, G, NE, 1, false);                        // G = Kh I_el^T
-        __syncthreads();
-        gemm(B, NQ, NE, G, NE, 1, S + dir * NQ * NE, 1, NE, acc, NQ, 1, dir > 0);   // acc (+)= G S^T
-    }
-    // faces: one lift of A+ x_own + A- f^h x_nbr per face
-    for (int s = 0; s < 4; ++s) {
-        const int32_t nu = neigh[e * 4 + s];
-        const bool has = nu >= 0 && nu < E;
-        // orientations above 2 are invalid input; they read f^0 so that the
-        // read stays inside the blob
-        const int j = face_rot[e * 4 + s] & 3, h0 = (face_rot[e * 4 + s] >> 2) & 3, h = h0 > 2 ? 0 : h0;
-        __syncthreads();
-        const double *to = traces + (e * 4 + s) * NE * Bf;
-        for (int i = threadIdx.x; i < NE * Bf; i += THREADS) {
-            const int q = i / Bf, m = i - q * Bf;
-            trO[m * NE + q] = to[i];
-        }
-        if (has) {
-            const double *tn = traces + ((int64_t)nu * 4 + j) * NE * Bf;
-            for (int i = threadIdx.x; i < NE * Bf; i += THREADS) {
-                const int q = i / Bf, m = i - q * Bf;
-                trN[m * NE + q] = tn[i];
-            }
-            copy(Mb, rf.f + h * Bf * Bf, Bf * Bf);
-            __syncthreads();
-            gemm(Bf, NE, Bf, Mb, Bf, 1, trN, NE, 1, X, NE, 1, false);                // X = f^h x_nbr
-        } else {
-            for (int i = threadIdx.x; i < NE * Bf; i += THREADS) X[i] = 0.0;
-        }
-        __syncthreads();
-        const double *ap = Ap + (e * 4 + s) * NQ * NE, *am = Am + (e * 4 + s) * NQ * NE;
-        for (int i = threadIdx.x; i < Bf * NQ; i += THREADS) {
-            const int m = i / NQ, p = i - m * NQ;
-            double v = 0.0;
 #pragma unroll
-            for (int q = 0; q < NE; ++q) v = fma(ap[p * NE + q], trO[m * NE + q], fma(am[p * NE + q], X[m * NE + q], v));
-            F[i] = v;
-        }
-        copy(Mb, rf.Rh + s * B * Bf, B * Bf);
-        __syncthreads();
-        gemm(B, NQ, Bf, Mb, Bf, 1, F, NQ, 1, acc, NQ, 1, true);                      // acc += Rh_s F
-    }
-    __syncthreads();
-    double *Qe = Q + e * NQ * B;
-    for (int i = threadIdx.x; i < NQ * B; i += THREADS) {
-        const int p = i / B, k = i - p * B;
-        Qe[i] += acc[k * NQ + p] + source(Is + k * NQ, p, om.w);
+    for (int s = 0; s < 7; ++s) {
+        const int k = 4 * s + lk, dir = k / NE;
+        sb[s] = (k < NQ && col < NQ) ? Se[(dir * NQ + col) * NE + (k - dir * NE)] : 0.0;
     }
 }
 
 template <int N>
-hipError_t step(int64_t E, double dt, double *Q, double *I, double *traces, const double *star, const double *Ap,
-                const double *Am, const int32_t *neigh, const uint8_t *face_rot, VOmega om, const double *blob,
-                hipStream_t s)
+__global__ void __launch_bounds__(THREADS)
+k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
-    static bool attr = false;      // the dynamic LDS limits, set once per degree
-    const size_t lp = (size_t)predict_lds<N>() * 8, lc = (size_t)correct_lds<N>() * 8;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_visco_predict<N>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_visco_correct<N>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lc);
-        if (e != hipSuccess) return e;
-        attr = true;
+    using Dm = Dim<N>;
+    constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, BP = Dm::BP, MT1 = Dm::MT1, MTf = Dm::MTf, OT = Dm::OT,
+                  TPW = Dm::TPW, QPT = Dm::QPT;
+    constexpr int KS = (B + 3) / 4;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double *const D = reinterpret_cast<double *>(lds_raw), *const Dn = D + B * NQ, *const G = Dn + B * NQ,
+                 *const Kt_l = G + B1 * NQ;
+    const double *Kt_g = blob + 3 * B * B, *R_g = blob + 6 * B * B;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int col = 16 * (wave & 1) + li;    // every tile a wave owns is in column block wave & 1
+    if constexpr (Dm::P_RES) {
+        for (int i = tid; i < 3 * B1 * B; i += THREADS) {
+            const int dr = i / B, k = i - dr * B, dir = dr / B1;
+            Kt_l[dr * BP + k] = Kt_g[(dir * B + (dr - dir * B1)) * B + k];
+        }
     }
-    hipLaunchKernelGGL(k_visco_predict<N>, dim3((unsigned)E), dim3(THREADS), lp, s, dt, Q, star, om, blob, I,
-                       traces);
+    // the next element's Q and star operands travel in registers
+    double qn[QPT], sn[7];
+    VItem it = items ? items[0] : one, nx = it;
+    int cur = 0, ncur = 0;
+    auto fetch = [&](int64_t gg) {
+        while (gg >= nx.first + nx.E) nx = items[++ncur];
+        const int64_t ee = gg - nx.first;
+        const double *Qe = nx.Q + ee * NQ * B;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int i = tid + u * THREADS;
+            qn[u] = i < NQ * B ? Qe[i] : 0.0;
+        }
+        star_b(nx.star + ee * 3 * NQ * NE, col, lk, sn);
+    };
+    if ((int64_t)blockIdx.x < total) fetch(blockIdx.x);
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        while (g >= it.first + it.E) it = items[++cur];
+        const int64_t e = g - it.first;
+        const double dt = it.dt, w0 = it.omega[0], w1 = it.omega[1], w2 = it.omega[2];
+        __syncthreads();    // the previous element's LDS reads are done (and Kt is staged)
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int i = tid + u * THREADS;
+            if (i < NQ * B) {
+                const int p = i / B, k = i - p * B;
+                D[k * NQ + p] = qn[u];
+            }
+        }
+        double sb[7];
+#pragma unroll
+        for (int s = 0; s < 7; ++s) sb[s] = sn[s];
+        if (g + gridDim.x < total) fetch(g + gridDim.x);
+        __syncthreads();
+        d4 Is[TPW];
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int t = wave + WAVES * j, mt = t >> 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * mt + lk + 4 * r;
+                Is[j][r] = (t < OT && row < B && col < NQ) ? dt * D[row * NQ + col] : 0.0;
+            }
+        }
+        double c = dt;
+        double *Dc = D, *Dx = Dn;
+        for (int d = 0; d < N; ++d) {
+            // G_dir = Kt_dir D_el over the rows of degree < N
+            for (int t = wave; t < 3 * MT1; t += WAVES) {
+                const int dir = t / MT1, mt = t - dir * MT1, i = 16 * mt + li;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int k = 4 * s + lk;
+                    double a = 0.0;
+                    if (i < B1 && k < B) {
+                        if constexpr (Dm::P_RES) a = Kt_l[(dir * B1 + i) * BP + k];
+                        else a = Kt_g[(dir * B + i) * B + k];
+                    }
+                    const double b = (k < B && li < NE) ? Dc[k * NQ + li] : 0.0;
+                    acc = mfma(a, b, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mt + lk + 4 * r;
+                    if (row < B1 && li < NE) G[row * NQ + dir * NE + li] = acc[r];
+                }
+            }
+            __syncthreads();
+            c *= dt / (d + 2);
+            // D^{d+1} = [G_1 G_2 G_3] [S_1 S_2 S_3]^T + E D^d;  I += dt^{d+2}/(d+2)! D^{d+1}
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int t = wave + WAVES * j;
+                if (t < OT) {
+                    const int mt = t >> 1, i = 16 * mt + li;
+                    d4 acc = {0.0, 0.0, 0.0, 0.0};
+                    if (16 * mt < B1) {
+#pragma unroll
+                        for (int s = 0; s < 7; ++s) {
+                            const int k = 4 * s + lk;
+                            acc = mfma((i < B1 && k < NQ) ? G[i * NQ + k] : 0.0, sb[s], acc);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * mt + lk + 4 * r;
+                        if (row < B && col < NQ) {
+                            const double v = acc[r] + source(Dc + row * NQ, col, w0, w1, w2);
+                            Dx[row * NQ + col] = v;
+                            Is[j][r] += c * v;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            double *tmp = Dc;
+            Dc = Dx;
+            Dx = tmp;
+        }
+        // the time integral to LDS (the buffer of the previous derivative), then out
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int t = wave + WAVES * j, mt = t >> 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * mt + lk + 4 * r;
+                if (t < OT && row < B && col < NQ) Dx[row * NQ + col] = Is[j][r];
+            }
+        }
+        __syncthreads();
+        double *Ie = it.I + e * NQ * B;
+        for (int i = tid; i < NQ * B; i += THREADS) {
+            const int p = i / B, k = i - p * B;
+            Ie[i] = Dx[k * NQ + p];
+        }
+        // face traces R_s^T I_el, stored [s][q][m]
+        double *te = it.traces + e * 4 * NE * Bf;
+        for (int t = wave; t < 4 * MTf; t += WAVES) {
+            const int s = t / MTf, mt = t - s * MTf, i = 16 * mt + li;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                const int k = 4 * st + lk;
+                const double a = (i < Bf && k < B) ? R_g[(s * B + k) * Bf + i] : 0.0;
+                const double b = (k < B && li < NE) ? Dx[k * NQ + li] : 0.0;
+                acc = mfma(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = 16 * mt + lk + 4 * r;
+                if (m < Bf && li < NE) te[(s * NE + li) * Bf + m] = acc[r];
+            }
+        }
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(THREADS)
+k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
+{
+    using Dm = Dim<N>;
+    constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, B1P = Dm::B1P, BfP = Dm::BfP, WP = Dm::WP, MT = Dm::MT,
+                  MTf = Dm::MTf, OT = Dm::OT, TPW = Dm::TPW;
+    constexpr int KS1 = (B1 + 3) / 4, KSF = (Bf + 3) / 4, KSR = (4 * Bf + 3) / 4;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double *const f_l = reinterpret_cast<double *>(lds_raw), *const Iel = f_l + 3 * Bf * BfP,
+                 *const G = Iel + B * NE, *const X = G + B * NQ, *const F = X + 4 * Bf * NE,
+                 *const To = F + 4 * Bf * NQ, *const Tn = To + 4 * NE * Bf, *const W = Tn + 4 * NE * BfP,
+                 *const Kh_l = W + 4 * NQ * WP;
+    const double *Kh_g = blob, *Rh_g = blob + 6 * B * B + 4 * B * Bf, *f_g = Rh_g + 4 * B * Bf;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int col = 16 * (wave & 1) + li;    // every owned output tile is in column block wave & 1
+    for (int i = tid; i < 3 * Bf * Bf; i += THREADS) {
+        const int r = i / Bf;
+        f_l[r * BfP + (i - r * Bf)] = f_g[i];
+    }
+    if constexpr (Dm::C_RES) {
+        for (int i = tid; i < 3 * B * B1; i += THREADS) {
+            const int dr = i / B1;
+            Kh_l[dr * B1P + (i - dr * B1)] = Kh_g[dr * B + (i - dr * B1)];
+        }
+    }
+    VItem it = items ? items[0] : one;
+    int cur = 0;
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        while (g >= it.first + it.E) it = items[++cur];
+        const int64_t e = g - it.first;
+        const double *Ig = it.I + e * NQ * B;
+        __syncthreads();    // the previous element's LDS reads are done (and f, Kh are staged)
+        // stage the element: elastic columns of I, own and neighbour traces, [A+ A-]
+        for (int i = tid; i < NE * B; i += THREADS) {
+            const int p = i / B, k = i - p * B;
+            Iel[k * NE + p] = Ig[i];
+        }
+        const double *to = it.traces + e * 4 * NE * Bf;
+        for (int i = tid; i < 4 * NE * Bf; i += THREADS) To[i] = to[i];
+        for (int i = tid; i < 4 * NE * Bf; i += THREADS) {
+            const int s = i / (NE * Bf), r = i - s * NE * Bf, q = r / Bf, m = r - q * Bf;
+            const int32_t nu = it.neigh[e * 4 + s];
+            double v = 0.0;
+            if (nu >= 0 && nu < it.E)
+                v = it.traces[(((int64_t)nu * 4 + (it.face_rot[e * 4 + s] & 3)) * NE + q) * Bf + m];
+            Tn[(s * NE + q) * BfP + m] = v;
+        }
+        const double *ap = it.Ap + e * 4 * NQ * NE, *am = it.Am + e * 4 * NQ * NE;
+        for (int i = tid; i < 4 * NQ * NE; i += THREADS) {
+            const int sp = i / NE, q = i - sp * NE;
+            W[sp * WP + q] = ap[i];
+            W[sp * WP + NE + q] = am[i];
+        }
+        double sb[7];
+        star_b(it.star + e * 3 * NQ * NE, col, lk, sb);
+        __syncthreads();
+        // phase A: G_dir = Kh_dir I_el (columns of degree < N);  X_s = f^h x_nbr
+        for (int t = wave; t < 3 * MT + 4 * MTf; t += WAVES) {
+            if (t < 3 * MT) {
+                const int dir = t / MT, mt = t - dir * MT, i = 16 * mt + li;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS1; ++s) {
+                    const int k = 4 * s + lk;
+                    double a = 0.0;
+                    if (i < B && k < B1) {
+                        if constexpr (Dm::C_RES) a = Kh_l[(dir * B + i) * B1P + k];
+                        else a = Kh_g[(dir * B + i) * B + k];
+                    }
+                    const double b = (k < B1 && li < NE) ? Iel[k * NE + li] : 0.0;
+                    acc = mfma(a, b, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mt + lk + 4 * r;
+                    if (row < B && li < NE) G[row * NQ + dir * NE + li] = acc[r];
+                }
+            } else {
+                const int tt = t - 3 * MT, s = tt / MTf, mt = tt - s * MTf, i = 16 * mt + li;
+                // orientations above 2 are invalid input; they read f^0 so
+                // that the read stays inside the matrix
+                const int h0 = (it.face_rot[e * 4 + s] >> 2) & 3, h = h0 > 2 ? 0 : h0;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < KSF; ++st) {
+                    const int k = 4 * st + lk;
+                    const double a = (i < Bf && k < Bf) ? f_l[(h * Bf + i) * BfP + k] : 0.0;
+                    const double b = (k < Bf && li < NE) ? Tn[(s * NE + li) * BfP + k] : 0.0;
+                    acc = mfma(a, b, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mt + lk + 4 * r;
+                    if (row < Bf && li < NE) X[(s * Bf + row) * NE + li] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // phase B: volume [G_1 G_2 G_3] [S_1 S_2 S_3]^T into the owned tiles;
+        // F_s = [x_own X_s] [A+_s A-_s]^T
+        d4 acc[TPW];
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int t = wave + WAVES * j, i = 16 * (t >> 1) + li;
+            acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+            if (t < OT) {
+#pragma unroll
+                for (int s = 0; s < 7; ++s) {
+                    const int k = 4 * s + lk;
+                    acc[j] = mfma((i < B && k < NQ) ? G[i * NQ + k] : 0.0, sb[s], acc[j]);
+                }
+            }
+        }
+        for (int t = wave; t < 8 * MTf; t += WAVES) {
+            const int s = t / (2 * MTf), r2 = t - s * 2 * MTf, mt = r2 >> 1;
+            const int i = 16 * mt + li, fc = 16 * (r2 & 1) + li;
+            d4 f = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < 5; ++st) {
+                const int k = 4 * st + lk;
+                double a = 0.0;
+                if (i < Bf) {
+                    if (k < NE) a = To[(s * NE + k) * Bf + i];
+                    else if (k < 2 * NE) a = X[(s * Bf + i) * NE + (k - NE)];
+                }
+                const double b = (fc < NQ && k < 2 * NE) ? W[(s * NQ + fc) * WP + k] : 0.0;
+                f = mfma(a, b, f);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * mt + lk + 4 * r;
+                if (row < Bf && fc < NQ) F[(s * Bf + row) * NQ + fc] = f[r];
+            }
+        }
+        __syncthreads();
+        // phase C: + sum_s Rh_s F_s as one product over K = 4 Bf; the result
+        // to LDS (G is free after phase B)
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int t = wave + WAVES * j, mt = t >> 1, i = 16 * mt + li;
+            if (t < OT) {
+#pragma unroll
+                for (int st = 0; st < KSR; ++st) {
+                    const int kk = 4 * st + lk, s = kk / Bf, m = kk - s * Bf;
+                    const double a = (i < B && kk < 4 * Bf) ? Rh_g[(s * B + i) * Bf + m] : 0.0;
+                    const double b = (kk < 4 * Bf && col < NQ) ? F[kk * NQ + col] : 0.0;
+                    acc[j] = mfma(a, b, acc[j]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mt + lk + 4 * r;
+                    if (row < B && col < NQ) G[row * NQ + col] = acc[j][r];
+                }
+            }
+        }
+        __syncthreads();
+        // Q += volume + fluxes + E I
+        double *Qe = it.Q + e * NQ * B;
+        for (int i = tid; i < NQ * B; i += THREADS) {
+            const int p = i / B, k = i - p * B;
+            double src = 0.0;
+            if (p < 6) src = -(Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
+            else if (p >= 9) src = -(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])) * Ig[i];
+            Qe[i] += G[k * NQ + p] + src;
+        }
+    }
+}
+
+template <typename K>
+hipError_t persistent_grid(K kernel, size_t lds, int *grid)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, THREADS, lds);
+    if (e != hipSuccess) return e;
+    *grid = cus * (per_cu > 0 ? per_cu : 1);
+    return hipSuccess;
+}
+
+template <int N>
+hipError_t step(const VItem *items, const VItem &one, int64_t total, const double *blob, hipStream_t s)
+{
+    using Dm = Dim<N>;
+    static int gp = 0, gc = 0;    // persistent grid sizes (CUs x resident workgroups), set once
+    const size_t lp = (size_t)Dm::P_LDS * 8, lc = (size_t)Dm::C_LDS * 8;
+    if (!gp || !gc) {
+        int a = 0, b = 0;
+        hipError_t e = persistent_grid(k_visco_predict<N>, lp, &a);
+        if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, lc, &b);
+        if (e != hipSuccess) return e;
+        gp = a, gc = b;
+    }
+    const unsigned np = (unsigned)(total < gp ? total : gp), nc = (unsigned)(total < gc ? total : gc);
+    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(THREADS), lp, s, items, one, total, blob);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_visco_correct<N>, dim3((unsigned)E), dim3(THREADS), lc, s, E, I, traces, star, Ap, Am,
-                       neigh, face_rot, om, blob, Q);
+    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(THREADS), lc, s, items, one, total, blob);
     return hipGetLastError();
 }
 
 }  // namespace dgv
 
-hipError_t visco_step_launch(int degree, int64_t E, double dt, double *Q, double *I, double *traces,
-                             const double *star, const double *Ap, const double *Am, const int32_t *neigh,
-                             const uint8_t *face_rot, VOmega om, const double *blob, hipStream_t s)
+hipError_t visco_step_launch(int degree, const VItem *items, int n_items, const VItem &one, int64_t total,
+                             const double *blob, hipStream_t s)
 {
+    if (total <= 0 || n_items <= 0) return hipSuccess;
     switch (degree) {
-    case 2: return dgv::step<2>(E, dt, Q, I, traces, star, Ap, Am, neigh, face_rot, om, blob, s);
-    case 3: return dgv::step<3>(E, dt, Q, I, traces, star, Ap, Am, neigh, face_rot, om, blob, s);
-    case 4: return dgv::step<4>(E, dt, Q, I, traces, star, Ap, Am, neigh, face_rot, om, blob, s);
-    case 5: return dgv::step<5>(E, dt, Q, I, traces, star, Ap, Am, neigh, face_rot, om, blob, s);
-    case 6: return dgv::step<6>(E, dt, Q, I, traces, star, Ap, Am, neigh, face_rot, om, blob, s);
+    case 2: return dgv::step<2>(items, one, total, blob, s);
+    case 3: return dgv::step<3>(items, one, total, blob, s);
+    case 4: return dgv::step<4>(items, one, total, blob, s);
+    case 5: return dgv::step<5>(items, one, total, blob, s);
+    case 6: return dgv::step<6>(items, one, total, blob, s);
     default: return hipErrorInvalidValue;
     }
 }
