@@ -382,8 +382,13 @@ int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, doub
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller
- * and must stay valid for the batch's lifetime; layouts as for dg_step with
- * the item's degree; element type per the batch precision. */
+ * and must stay valid for the batch's lifetime.  Elastic items (n_quant 9):
+ * layouts as for dg_step with the item's degree, element type per the batch
+ * precision.  Viscoelastic items (n_quant 27, DG_FP64 batches only): layouts
+ * as for dg_visco_step, FP64: Q and I [E][27][B], traces [E][4][9][Bf],
+ * star_packed the viscoelastic star matrices [E][3][27][9] and Aplus, Aminus
+ * [E][4][27][9] as dg_visco_element_data_host writes them, and omega the
+ * relaxation frequencies of the item's three mechanisms. */
 typedef struct {
     int degree;                 /* 2..6 */
     int64_t E;                  /* elements of this mesh (>= 0) */
@@ -393,6 +398,8 @@ typedef struct {
     const double *Aplus, *Aminus;
     const int32_t *neigh;       /* indices local to this mesh, in [0, E) */
     const uint8_t *face_rot;
+    int n_quant;                /* 9 (elastic; 0 is read as 9) or 27 (viscoelastic) */
+    double omega[3];            /* viscoelastic items: relaxation frequencies (finite, >= 0) */
 } dg_batch_item;
 
 typedef struct dg_batch dg_batch;
@@ -400,10 +407,13 @@ typedef struct dg_batch dg_batch;
 /* Builds the work tables of a batch (device memory owned by the batch; this
  * call allocates, and uploads on a private stream that it waits for).  One
  * time step of a batch is one predictor launch and one corrector launch per
- * degree present, over all
- * meshes of that degree; the launches of a step are recorded once into a HIP
- * graph and replayed.  Each element's arithmetic is identical to dg_step's,
- * so a mesh gives bitwise the same result alone and in any batch. */
+ * degree and material model present, over all meshes of that degree and
+ * model (the viscoelastic launches are persistent workgroups walking the
+ * elements of all their meshes); the launches of a step are recorded once
+ * into a HIP graph and replayed.  Each element's arithmetic is identical to
+ * dg_step's (elastic) or dg_visco_step's (viscoelastic), so a mesh gives
+ * bitwise the same result alone and in any batch.  DG_EUNSUPPORTED for a
+ * viscoelastic item in a batch that is not DG_FP64. */
 int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_items, dg_batch **out);
 /* n_steps time steps of every mesh of the batch, stream ordered. */
 int dg_batch_step(dg_batch *batch, int n_steps, hipStream_t stream);

@@ -19,7 +19,8 @@ class BatchItem(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("E", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("Q", ctypes.c_void_p), ("I", ctypes.c_void_p), ("traces", ctypes.c_void_p),
                 ("star_packed", ctypes.c_void_p), ("Aplus", ctypes.c_void_p), ("Aminus", ctypes.c_void_p),
-                ("neigh", ctypes.c_void_p), ("face_rot", ctypes.c_void_p)]
+                ("neigh", ctypes.c_void_p), ("face_rot", ctypes.c_void_p), ("n_quant", ctypes.c_int),
+                ("omega", ctypes.c_double * 3)]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libdg_mi355x.so"
@@ -466,10 +467,13 @@ class Plan:
 
 class Batch:
     """A batch of independent meshes (any degrees) stepped together: one
-    predictor and one corrector launch per degree present, replayed as a HIP
-    graph.  `meshes` is a list of dicts with keys degree, E, dt, Q, I, traces,
-    star_packed, Aplus, Aminus, neigh, face_rot (device tensors owned by the
-    caller and kept alive by this object)."""
+    predictor and one corrector launch per degree and material model present,
+    replayed as a HIP graph.  `meshes` is a list of dicts with keys degree, E,
+    dt, Q, I, traces, star_packed, Aplus, Aminus, neigh, face_rot (device
+    tensors owned by the caller and kept alive by this object).  A
+    viscoelastic mesh (DG_FP64 batches) has n_quant=27, omega (3 relaxation
+    frequencies), star (E, 3, 27, 9) in place of star_packed, Q and I
+    (E, 27, B), traces (E, 4, 9, Bf) and Aplus, Aminus (E, 4, 27, 9)."""
 
     def __init__(self, precision, meshes):
         lib = _load()
@@ -489,6 +493,21 @@ class Batch:
             N, E = int(m["degree"]), int(m["E"])
             B, Bf = comb(N + 3, 3), comb(N + 2, 2)
             chk = Plan._check_tensor
+            if int(m.get("n_quant", 9)) == 27:
+                f64 = torch.float64
+                om = [float(w) for w in m["omega"]]
+                if len(om) != 3:
+                    raise ValueError("omega must hold 3 values")
+                arr[i] = BatchItem(N, E, float(m["dt"]),
+                                   chk(m["Q"], (E, 27, B), f64, "Q"), chk(m["I"], (E, 27, B), f64, "I"),
+                                   chk(m["traces"], (E, 4, 9, Bf), f64, "traces"),
+                                   chk(m["star"], (E, 3, 27, 9), f64, "star"),
+                                   chk(m["Aplus"], (E, 4, 27, 9), f64, "Aplus"),
+                                   chk(m["Aminus"], (E, 4, 27, 9), f64, "Aminus"),
+                                   chk(m["neigh"], (E, 4), torch.int32, "neigh"),
+                                   chk(m["face_rot"], (E, 4), torch.uint8, "face_rot"), 27,
+                                   (ctypes.c_double * 3)(*om))
+                continue
             arr[i] = BatchItem(N, E, float(m["dt"]),
                                chk(m["Q"], (E, 9, B), dt_, "Q"), chk(m["I"], (E, 9, B), dt_, "I"),
                                chk(m["traces"], (E, 4, 9 * Bf), dt_, "traces"),
@@ -496,7 +515,7 @@ class Batch:
                                chk(m["Aplus"], (E, 4, 9, 9), torch.float64, "Aplus"),
                                chk(m["Aminus"], (E, 4, 9, 9), torch.float64, "Aminus"),
                                chk(m["neigh"], (E, 4), torch.int32, "neigh"),
-                               chk(m["face_rot"], (E, 4), torch.uint8, "face_rot"))
+                               chk(m["face_rot"], (E, 4), torch.uint8, "face_rot"), 9)
         return arr, list(meshes)
 
     def update(self, meshes):

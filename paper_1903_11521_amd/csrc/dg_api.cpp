@@ -16,6 +16,7 @@
 
 #include "dg_internal.h"
 #include "refmat.h"
+#include "visco_internal.h"
 
 namespace {
 
@@ -551,8 +552,15 @@ struct dg_batch {
         size_t cap_items = 0, cap_blocks = 0;
         int64_t n_items = 0, nblocks = 0;
     };
+    struct VGroup {                // viscoelastic meshes of one degree
+        VItem *d_items = nullptr;
+        size_t cap = 0;
+        int n_items = 0;
+        int64_t total = 0;         // elements over the group's meshes
+    };
     struct Slot {
         Group groups[7];           // by degree
+        VGroup vgroups[7];
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         hipEvent_t last_use = nullptr;
@@ -565,6 +573,8 @@ struct dg_batch {
     hipStream_t aux = nullptr;     // private stream: table uploads and capture
     std::vector<DgItem> h_items;
     std::vector<int32_t> h_blocks;
+    std::vector<VItem> h_vitems;
+    double *vblob[7] = {};         // reference matrices of the viscoelastic degrees (device)
     ~dg_batch()
     {
         for (auto &sl : slot) {
@@ -576,19 +586,34 @@ struct dg_batch {
                 if (g.d_items) (void)hipFree(g.d_items);
                 if (g.d_block_item) (void)hipFree(g.d_block_item);
             }
+            for (auto &v : sl.vgroups)
+                if (v.d_items) (void)hipFree(v.d_items);
         }
+        for (double *p : vblob)
+            if (p) (void)hipFree(p);
         if (aux) (void)hipStreamDestroy(aux);
     }
 };
 
 namespace {
 
-int check_batch_items(const dg_batch_item *items, int n_items)
+bool is_visco(const dg_batch_item &x) { return x.n_quant == 27; }
+
+int check_batch_items(dg_precision prec, const dg_batch_item *items, int n_items)
 {
     if (n_items < 0 || (n_items > 0 && !items)) return fail(DG_EINVAL, "bad item list%s", "");
     for (int i = 0; i < n_items; ++i) {
         const dg_batch_item &x = items[i];
         if (x.degree < 2 || x.degree > 6) return fail(DG_EUNSUPPORTED, "item degree %s%lld outside 2..6", "", x.degree);
+        if (x.n_quant != 0 && x.n_quant != 9 && x.n_quant != 27)
+            return fail(DG_EINVAL, "item quantity count %s%lld is neither 9 nor 27", "", x.n_quant);
+        if (is_visco(x)) {
+            if (prec != DG_FP64)
+                return fail(DG_EUNSUPPORTED, "viscoelastic items need a DG_FP64 batch%s", "");
+            for (double w : x.omega)
+                if (!(w >= 0.0) || w > 1e300)
+                    return fail(DG_EINVAL, "item relaxation frequencies must be finite and >= 0%s", "");
+        }
         CHECK_E(x.E);
         CHECK_PTR(x.E, x.Q, "item Q");
         CHECK_PTR(x.E, x.I, "item I");
@@ -617,7 +642,7 @@ hipError_t ensure(void **p, size_t *cap, size_t bytes)
     return hipSuccess;
 }
 
-hipError_t batch_enqueue(dg_batch::Slot &sl, hipStream_t s)
+hipError_t batch_enqueue(const dg_batch *b, dg_batch::Slot &sl, hipStream_t s)
 {
     for (auto &g : sl.groups) {
         if (!g.nblocks) continue;
@@ -627,6 +652,13 @@ hipError_t batch_enqueue(dg_batch::Slot &sl, hipStream_t s)
     for (auto &g : sl.groups) {
         if (!g.nblocks) continue;
         hipError_t e = g.tab.batch_correct(g.d_items, g.d_block_item, g.nblocks, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int deg = 2; deg <= 6; ++deg) {
+        const dg_batch::VGroup &v = sl.vgroups[deg];
+        if (!v.total) continue;
+        const VItem none{};
+        hipError_t e = visco_step_launch(deg, v.d_items, v.n_items, none, v.total, b->vblob[deg], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -659,7 +691,7 @@ int batch_fill(dg_batch *b, int k, const dg_batch_item *items, int n_items)
         int64_t nb = 0;
         for (int i = 0; i < n_items; ++i) {
             const dg_batch_item &x = items[i];
-            if (x.degree != deg || x.E == 0) continue;
+            if (x.degree != deg || x.E == 0 || is_visco(x)) continue;
             DgItem it = make_item(x.E, x.dt, x.Q, x.I, x.traces, x.star_packed, x.Aplus, x.Aminus, x.neigh,
                                   x.face_rot);
             it.first_block = nb;
@@ -686,11 +718,54 @@ int batch_fill(dg_batch *b, int k, const dg_batch_item *items, int n_items)
         if (e == hipSuccess) e = hipStreamSynchronize(b->aux);
         if (e != hipSuccess) return hip_status(e, "dg_batch (tables)");
     }
+    // viscoelastic meshes: one work list per degree
+    for (int deg = 2; deg <= 6; ++deg) {
+        dg_batch::VGroup &V = sl.vgroups[deg];
+        b->h_vitems.clear();
+        int64_t total = 0;
+        for (int i = 0; i < n_items; ++i) {
+            const dg_batch_item &x = items[i];
+            if (x.degree != deg || x.E == 0 || !is_visco(x)) continue;
+            VItem v{};
+            v.E = x.E;
+            v.first = total;
+            v.dt = x.dt;
+            for (int l = 0; l < 3; ++l) v.omega[l] = x.omega[l];
+            v.Q = static_cast<double *>(x.Q), v.I = static_cast<double *>(x.I);
+            v.traces = static_cast<double *>(x.traces);
+            v.star = static_cast<const double *>(x.star_packed), v.Ap = x.Aplus, v.Am = x.Aminus;
+            v.neigh = x.neigh, v.face_rot = x.face_rot;
+            b->h_vitems.push_back(v);
+            total += x.E;
+        }
+        V.n_items = (int)b->h_vitems.size();
+        V.total = total;
+        if (!total) continue;
+        sl.empty = false;
+        hipError_t e = hipSuccess;
+        if (!b->vblob[deg]) {
+            std::vector<double> blob(dgref::blob_size(deg));
+            if (dgref::build(deg, blob.data()) != 0) return fail(DG_EINVAL, "reference matrix build failed%s", "");
+            e = hipMalloc(reinterpret_cast<void **>(&b->vblob[deg]), blob.size() * sizeof(double));
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->vblob[deg], blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   b->aux);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->aux);
+        }
+        if (e == hipSuccess)
+            e = ensure(reinterpret_cast<void **>(&V.d_items), &V.cap, sizeof(VItem) * b->h_vitems.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(V.d_items, b->h_vitems.data(), sizeof(VItem) * b->h_vitems.size(),
+                               hipMemcpyHostToDevice, b->aux);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->aux);
+        if (e == hipSuccess) e = visco_prepare(deg);
+        if (e != hipSuccess) return hip_status(e, "dg_batch (viscoelastic tables)");
+    }
     if (sl.empty) return DG_OK;
     // record one step into a graph on the private stream
     hipError_t e = hipStreamBeginCapture(b->aux, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_status(e, "dg_batch (capture)");
-    hipError_t le = batch_enqueue(sl, b->aux);
+    hipError_t le = batch_enqueue(b, sl, b->aux);
     e = hipStreamEndCapture(b->aux, &sl.graph);
     if (le != hipSuccess) return hip_status(le, "dg_batch (launch)");
     if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
@@ -708,7 +783,7 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
     *out = nullptr;
     if (precision != DG_FP64 && precision != DG_FP32 && precision != DG_MIXED)
         return fail(DG_EUNSUPPORTED, "unsupported batch precision %s%lld", "", (long long)precision);
-    int rc = check_batch_items(items, n_items);
+    int rc = check_batch_items(precision, items, n_items);
     if (rc != DG_OK) return rc;
     std::unique_ptr<dg_batch> b(new (std::nothrow) dg_batch);
     if (!b) return fail(DG_ENOMEM, "out of host memory%s", "");
@@ -727,7 +802,7 @@ int dg_batch_create(dg_precision precision, const dg_batch_item *items, int n_it
 int dg_batch_update(dg_batch *b, const dg_batch_item *items, int n_items)
 {
     if (!b) return fail(DG_EINVAL, "null batch%s", "");
-    int rc = check_batch_items(items, n_items);
+    int rc = check_batch_items(b->prec, items, n_items);
     if (rc != DG_OK) return rc;
     const int k = 1 - b->cur;
     rc = batch_fill(b, k, items, n_items);

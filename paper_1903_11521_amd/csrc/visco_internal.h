@@ -25,3 +25,7 @@ struct VItem {
 // device.
 hipError_t visco_step_launch(int degree, const VItem *items, int n_items, const VItem &one, int64_t total,
                              const double *blob, hipStream_t s);
+
+// Sets the kernels' LDS limits and persistent grid sizes for a degree (done
+// by the first launch otherwise; call before recording launches into a graph).
+hipError_t visco_prepare(int degree);

@@ -442,27 +442,53 @@ hipError_t persistent_grid(K kernel, size_t lds, int *grid)
 }
 
 template <int N>
+struct Grid {
+    static inline int predict = 0, correct = 0;    // CUs x resident workgroups, set once
+};
+
+template <int N>
+hipError_t prepare()
+{
+    using Dm = Dim<N>;
+    if (Grid<N>::predict && Grid<N>::correct) return hipSuccess;
+    int a = 0, b = 0;
+    hipError_t e = persistent_grid(k_visco_predict<N>, (size_t)Dm::P_LDS * 8, &a);
+    if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, (size_t)Dm::C_LDS * 8, &b);
+    if (e != hipSuccess) return e;
+    Grid<N>::predict = a, Grid<N>::correct = b;
+    return hipSuccess;
+}
+
+template <int N>
 hipError_t step(const VItem *items, const VItem &one, int64_t total, const double *blob, hipStream_t s)
 {
     using Dm = Dim<N>;
-    static int gp = 0, gc = 0;    // persistent grid sizes (CUs x resident workgroups), set once
-    const size_t lp = (size_t)Dm::P_LDS * 8, lc = (size_t)Dm::C_LDS * 8;
-    if (!gp || !gc) {
-        int a = 0, b = 0;
-        hipError_t e = persistent_grid(k_visco_predict<N>, lp, &a);
-        if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, lc, &b);
-        if (e != hipSuccess) return e;
-        gp = a, gc = b;
-    }
-    const unsigned np = (unsigned)(total < gp ? total : gp), nc = (unsigned)(total < gc ? total : gc);
-    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(THREADS), lp, s, items, one, total, blob);
-    hipError_t e = hipGetLastError();
+    hipError_t e = prepare<N>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(THREADS), lc, s, items, one, total, blob);
+    const int64_t gp = Grid<N>::predict, gc = Grid<N>::correct;
+    const unsigned np = (unsigned)(total < gp ? total : gp), nc = (unsigned)(total < gc ? total : gc);
+    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(THREADS), (size_t)Dm::P_LDS * 8, s, items, one, total,
+                       blob);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(THREADS), (size_t)Dm::C_LDS * 8, s, items, one, total,
+                       blob);
     return hipGetLastError();
 }
 
 }  // namespace dgv
+
+hipError_t visco_prepare(int degree)
+{
+    switch (degree) {
+    case 2: return dgv::prepare<2>();
+    case 3: return dgv::prepare<3>();
+    case 4: return dgv::prepare<4>();
+    case 5: return dgv::prepare<5>();
+    case 6: return dgv::prepare<6>();
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t visco_step_launch(int degree, const VItem *items, int n_items, const VItem &one, int64_t total,
                              const double *blob, hipStream_t s)

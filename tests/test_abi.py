@@ -201,3 +201,27 @@ def test_visco_element_data_matches_oracle():
     for got, ref in ((star, ostar[..., :9]), (Ap, oAp[..., :9]), (Am, oAm[..., :9])):
         assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
     assert np.all(Am[0, 2] == 0)
+
+
+def test_batch_item_argument_errors():
+    """Batch items are checked before anything touches the device: quantity
+    counts other than 9 and 27, viscoelastic items outside an FP64 batch and
+    bad relaxation frequencies."""
+    import ctypes
+    import paper_1903_11521_amd._lib as L
+    lib = L._load()
+    fake = 1 << 20                               # never dereferenced: the checks fail first
+
+    def item(n_quant, omega=(1.0, 2.0, 3.0)):
+        return L.BatchItem(3, 10, 1e-3, fake, fake, fake, fake, fake, fake, fake, fake, n_quant,
+                           (ctypes.c_double * 3)(*omega))
+    out = ctypes.c_void_p()
+    arr = (L.BatchItem * 1)(item(12))
+    assert lib.dg_batch_create(0, arr, 1, ctypes.byref(out)) == -1 and b"neither 9 nor 27" in lib.dg_last_error()
+    arr = (L.BatchItem * 1)(item(27))
+    assert lib.dg_batch_create(1, arr, 1, ctypes.byref(out)) == -2 and b"DG_FP64" in lib.dg_last_error()
+    arr = (L.BatchItem * 1)(item(27, (1.0, -1.0, 2.0)))
+    assert lib.dg_batch_create(0, arr, 1, ctypes.byref(out)) == -1 and b"relaxation" in lib.dg_last_error()
+    arr = (L.BatchItem * 1)(item(27, (1.0, float("nan"), 2.0)))
+    assert lib.dg_batch_create(0, arr, 1, ctypes.byref(out)) == -1 and b"relaxation" in lib.dg_last_error()
+    assert not out.value

@@ -90,3 +90,53 @@ def test_visco_two_steps_and_missing_neighbours():
     ref = _oracle(N, *case, 2, neigh=nb)
     Q = case[-1]
     assert_close(got - Q, ref - Q, 1e-12, "two-step increment")
+
+
+def _visco_mesh(dg, N, n, seed):
+    """Device arrays of one viscoelastic mesh as a batch item."""
+    mesh, mats, dt, omega, Ylam, Ymu, Q = _case(N, n, seed)
+    star, Ap, Am = dg.visco_element_data(mesh.X, mats, omega, Ylam, Ymu, mesh.neigh)
+    E, Bf = mesh.E, refmat.refmats(N).Bf
+    item = dict(degree=N, E=E, dt=dt, n_quant=27, omega=omega, Q=_dev(Q), I=torch.empty((E, 27, Q.shape[2]),
+                dtype=torch.float64, device="cuda:0"),
+                traces=torch.empty((E, 4, 9, Bf), dtype=torch.float64, device="cuda:0"), star=_dev(star),
+                Aplus=_dev(Ap), Aminus=_dev(Am), neigh=_dev(mesh.neigh.astype(np.int32)), face_rot=_dev(mesh.face_rot))
+    return item, (mesh, mats, dt, omega, Ylam, Ymu, Q)
+
+
+def test_visco_meshes_in_a_mixed_batch():
+    """Two viscoelastic meshes (degrees 3 and 5) and an elastic one (degree 4)
+    in one FP64 batch, two steps: each viscoelastic mesh equals
+    dg_visco_step alone bitwise and the oracle to the bar; the elastic mesh
+    equals dg_step alone bitwise."""
+    _say("test_visco_meshes_in_a_mixed_batch")
+    import paper_1903_11521_amd as dg
+    from workload import cube_mesh, dt_from_mesh, random_dofs, random_materials, seed_for
+    v3, c3 = _visco_mesh(dg, 3, 3, 41)
+    v5, c5 = _visco_mesh(dg, 5, 3, 42)
+    mesh = cube_mesh(3, seed_for(43), relabel=True)
+    mats = random_materials(mesh.E, seed_for(43))
+    plan = dg.Plan(4, dg.DG_FP64)
+    star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
+    Qe = random_dofs(mesh.E, 9, plan.B, 43)
+    el = dict(degree=4, E=mesh.E, dt=dt_from_mesh(mesh, mats), Q=_dev(Qe),
+              I=torch.empty(plan.dof_shape(mesh.E), dtype=torch.float64, device="cuda:0"),
+              traces=torch.empty(plan.trace_shape(mesh.E), dtype=torch.float64, device="cuda:0"),
+              star_packed=plan.pack_star(_dev(star)), Aplus=_dev(Ap), Aminus=_dev(Am), neigh=_dev(mesh.neigh),
+              face_rot=_dev(mesh.face_rot))
+    batch = dg.Batch(dg.DG_FP64, [v3, el, v5])
+    batch.step(2)
+    torch.cuda.synchronize()
+    for item, case in ((v3, c3), (v5, c5)):
+        N = item["degree"]
+        alone = _gpu(N, *case, 2)
+        got = item["Q"].cpu().numpy()
+        assert np.array_equal(got, alone), "degree %d: batch differs from dg_visco_step" % N
+        ref = _oracle(N, *case, 2)
+        assert_close(got - case[-1], ref - case[-1], 1e-12, "degree %d in batch" % N)
+    Qa = _dev(Qe)
+    plan.step(Qa, torch.empty_like(el["I"]), torch.empty_like(el["traces"]), el["star_packed"], el["Aplus"],
+              el["Aminus"], el["neigh"], el["face_rot"], el["dt"], 2)
+    torch.cuda.synchronize()
+    assert torch.equal(Qa, el["Q"])
+    batch.close()
