@@ -53,6 +53,7 @@ def parse():
                          "lina: the LinA ADER-DG-SEM scheme on cuboids (Sec. 5.2)")
     ap.add_argument("--grading", type=float, default=64.0, help="lts: cell-width ratio across the graded mesh")
     ap.add_argument("--meshes", type=int, default=32)
+    ap.add_argument("--elastic-only", action="store_true", help="batched: no viscoelastic meshes")
     ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -139,7 +140,12 @@ def batched(args):
     """32 independent cube-split meshes, E_i ~ log-uniform[10k, 200k] elements
     (n_i = round((E_i/6)^(1/3)) cubes per direction), degree U{2..6}, random
     materials and N(0,1) DOFs per mesh; all stepped together (one predictor and
-    one corrector launch per degree, recorded once in a HIP graph)."""
+    one corrector launch per degree and material model, recorded once in a HIP
+    graph).  In FP64 every second mesh is viscoelastic (27 quantities, three
+    mechanisms with relaxation frequencies f ~ log-uniform[0.1, 10] Hz,
+    omega = 2 pi f, memory coefficients Y = (lambda, mu) * U[0.01, 0.05] per
+    mechanism); the other precisions have no viscoelastic form, so their
+    batches are elastic only."""
     import torch
 
     import paper_1903_11521_amd as dg
@@ -152,13 +158,27 @@ def batched(args):
     from paper_1903_11521_amd import perfmodel as pm
     itemsize = 8 if prec == dg.DG_FP64 else 4
     meshes, flops, nbytes = [], 0.0, 0.0
+    visco_on = prec == dg.DG_FP64 and not args.elastic_only
+    kinds = []
     for i, (Ei, N) in enumerate(zip(sizes, degrees)):
         n = max(3, int(round((Ei / 6) ** (1 / 3))))
         seed = seed_for(2) + 1000 * (i + 1)
         mesh = cube_mesh(n, seed)
         E = mesh.E
-        plan = dg.Plan(int(N), prec)
         mats = random_materials(E, seed)
+        if visco_on and i % 2 == 1:
+            vr = np.random.Generator(np.random.PCG64(seed + 7))
+            omega = 2 * np.pi * np.exp(vr.uniform(np.log(0.1), np.log(10.0), 3))
+            item = visco_mesh_item(dg, mesh, mats, int(N), omega, vr.uniform(0.01, 0.05, 3), seed, dev)
+            item["dt"] = dt_from_mesh(mesh, mats)
+            meshes.append(item)
+            kinds.append("visco")
+            f_, b_ = visco_model(int(N))
+            flops += f_ * E
+            nbytes += b_ * E
+            continue
+        kinds.append("elastic")
+        plan = dg.Plan(int(N), prec)
         Q = random_dofs(E, 9, plan.B, seed)
         star, Ap, Am = dg.element_data(mesh.X, mats, mesh.neigh)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -188,10 +208,12 @@ def batched(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": DTYPES[args.precision], "data": "synthetic",
-           "config": {"workload": "batched: %d independent elastic cube-split meshes, %d elements in total, "
-                                  "log-uniform 10k-200k elements per mesh, degrees uniform in 2..6, one HIP graph "
-                                  "replay per step" % (len(meshes), total),
-                      "elements": total, "degrees": degrees.tolist(), "mesh_elements": [m["E"] for m in meshes]},
+           "config": {"workload": "batched: %d independent cube-split meshes (%d viscoelastic with 3 "
+                                  "mechanisms, the rest elastic), %d elements in total, log-uniform 10k-200k "
+                                  "elements per mesh, degrees uniform in 2..6, one HIP graph replay per step"
+                                  % (len(meshes), kinds.count("visco"), total),
+                      "elements": total, "degrees": degrees.tolist(), "mesh_elements": [m["E"] for m in meshes],
+                      "models": kinds},
            "useful_gflops": flops * args.steps / el / 1e9, "roofline": roof}
     batch.close()
     print(json.dumps(out), flush=True)
@@ -418,6 +440,41 @@ def lina(args):
     print(json.dumps(out), flush=True)
 
 
+def visco_model(N):
+    """Useful flops and algorithmic bytes per viscoelastic element update at
+    degree N: the executed contractions over the 9 elastic columns the
+    Jacobians read (predictor recursion, traces, volume, the four faces' f^h,
+    flux-solver and lift products) and the source terms; Q read twice and
+    written, the time integral written and read, the traces written and read
+    (own and neighbour), the star matrices read twice, the flux solvers read
+    once, the neighbour table."""
+    from math import comb
+    B, Bf = comb(N + 3, 3), comb(N + 2, 2)
+    star_fl = 3 * (2 * B * B * 9 + 2 * B * 9 * 27)
+    flops = (N + 1) * star_fl + 4 * 2 * B * Bf * 9 + 4 * (2 * Bf * Bf * 9 + 4 * Bf * 27 * 9 + 2 * B * Bf * 27) \
+        + (N + 1) * (36 + 2 * 27) * B
+    nbytes = 8 * (3 * 27 * B + 2 * 27 * B + 3 * 4 * 9 * Bf + 2 * 3 * 27 * 9 + 2 * 4 * 27 * 9) + 4 * 5
+    return flops, nbytes
+
+
+def visco_mesh_item(dg, mesh, mats, N, omega, yfac, seed, dev):
+    """Device arrays of one viscoelastic mesh (batch item): memory
+    coefficients Y = (lambda, mu) * yfac per mechanism, N(0,1) DOFs."""
+    import torch
+    from math import comb
+    mu = mats[:, 0] * mats[:, 2] ** 2                    # rho cs^2
+    lam = mats[:, 0] * mats[:, 1] ** 2 - 2.0 * mu        # rho cp^2 - 2 mu
+    Ylam, Ymu = lam[:, None] * yfac[None, :], mu[:, None] * yfac[None, :]
+    star, Ap, Am = dg.visco_element_data(mesh.X, mats, omega, Ylam, Ymu, mesh.neigh)
+    E, B, Bf = mesh.E, comb(N + 3, 3), comb(N + 2, 2)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    from workload import random_dofs
+    return dict(degree=N, E=E, n_quant=27, omega=omega, Q=t(random_dofs(E, 27, B, seed)),
+                I=torch.empty((E, 27, B), dtype=torch.float64, device=dev),
+                traces=torch.empty((E, 4, 9, Bf), dtype=torch.float64, device=dev), star=t(star), Aplus=t(Ap),
+                Aminus=t(Am), neigh=t(mesh.neigh.astype(np.int32)), face_rot=t(mesh.face_rot))
+
+
 def visco(args):
     """Viscoelastic elements (27 quantities, three mechanisms) on the
     n x n x n cube-split mesh with random materials, degrees 3 and the
@@ -469,10 +526,7 @@ def visco(args):
         e1.record()
         torch.cuda.synchronize()
         el = e0.elapsed_time(e1) / 1e3 / steps
-        star_fl = 3 * (2 * B * B * 9 + 2 * B * 9 * 27)
-        flops = (N + 1) * star_fl + 4 * 2 * B * Bf * 9 + 4 * (2 * Bf * Bf * 9 + 4 * Bf * 27 * 9 + 2 * B * Bf * 27) \
-            + (N + 1) * (36 + 2 * 27) * B
-        nbytes = 8 * (3 * 27 * B + 2 * 27 * B + 3 * 4 * 9 * Bf + 2 * 3 * 27 * 9 + 2 * 4 * 27 * 9) + 4 * 5
+        flops, nbytes = visco_model(N)
         roof = pm.kernel_roofline(flops * E, nbytes * E, el, "f64")
         rows.append({"degree": N, "elements": E, "ms_per_step": el * 1e3, "element_updates_per_s": E / el,
                      "useful_gflops": flops * E / el / 1e9, "flops_per_element": flops,
