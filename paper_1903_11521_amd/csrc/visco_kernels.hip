@@ -43,7 +43,7 @@ using dgk::nb2;
 using dgk::nb3;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int NQ = 27, NE = 9, THREADS = 256, WAVES = THREADS / 64;
+constexpr int NQ = 27, NE = 9;
 constexpr int LDS_TWO_PER_CU = 80 * 1024;
 
 // polynomial degree of basis function r (the basis is ordered by degree)
@@ -60,12 +60,19 @@ struct Dim {
     // odd row strides of the LDS matrices read 16 rows at a time (no bank conflicts)
     static constexpr int BP = B | 1, B1P = B1 | 1, BfP = Bf | 1, WP = 19;
     static constexpr int MT = (B + 15) / 16, MT1 = (B1 + 15) / 16, MTf = (Bf + 15) / 16;
+    // workgroup: 4 waves, 8 at degree 6 (whose LDS admits one workgroup per CU)
+    static constexpr int T = N == 6 ? 512 : 256, WV = T / 64;
     static constexpr int OT = 2 * MT;                      // 16 x 16 tiles of a [B][27] array
-    static constexpr int TPW = (OT + WAVES - 1) / WAVES;   // of them owned per wave
-    static constexpr int QPT = (NQ * B + THREADS - 1) / THREADS;
+    static constexpr int TPW = (OT + WV - 1) / WV;         // of them owned per wave
+    static constexpr int QPT = (NQ * B + T - 1) / T;
+    // the predictor prefetches the next element into registers below degree 6
+    // (at degree 6 the registers go to two waves per SIMD instead)
+    static constexpr bool P_PF = N <= 5;
     // predictor LDS (doubles): D, Dn [B][27], G [B1][27]; Kt rows of degree < N [3][B1][BP] if resident
     static constexpr int P_EL = 2 * B * NQ + B1 * NQ, P_KT = 3 * B1 * BP;
-    static constexpr bool P_RES = 8 * (P_EL + P_KT) <= LDS_TWO_PER_CU;
+    // resident where two workgroups per CU fit; at degree 6 (one wave per
+    // SIMD for its registers anyway) resident in the whole LDS
+    static constexpr bool P_RES = 8 * (P_EL + P_KT) <= (N == 6 ? 160 * 1024 : LDS_TWO_PER_CU);
     static constexpr int P_LDS = P_EL + (P_RES ? P_KT : 0);
     // corrector LDS: f [3][Bf][BfP], I_el [B][9], G [B][27], X [4 Bf][9], F [4 Bf][27],
     // own traces [4][9][Bf], neighbour traces [4][9][BfP], [A+ A-] [4][27][WP];
@@ -101,14 +108,64 @@ __device__ __forceinline__ void star_b(const double *Se, int col, int lk, double
     }
 }
 
+// One 16-row tile of G_dir = Kt_dir D_el (rows of degree < N; columns of
+// degree <= the tile's lowest row degree are zero and skipped).
+template <int N, int MTI, bool RES>
+__device__ __forceinline__ d4 kt_tile(const double *Kt_l, const double *Kt_g, const double *Dc, int dir, int li,
+                                      int lk)
+{
+    using Dm = Dim<N>;
+    constexpr int B = Dm::B, B1 = Dm::B1, BP = Dm::BP, KS = (B + 3) / 4, KS0 = nb3(deg_of(16 * MTI)) / 4;
+    const int i = 16 * MTI + li;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = KS0; s < KS; ++s) {
+        const int k = 4 * s + lk;
+        double a = 0.0;
+        if (i < B1 && k < B) {
+            if constexpr (RES) a = Kt_l[(dir * B1 + i) * BP + k];
+            else a = Kt_g[(dir * B + i) * B + k];
+        }
+        const double b = (k < B && li < NE) ? Dc[k * NQ + li] : 0.0;
+        acc = mfma(a, b, acc);
+    }
+    return acc;
+}
+
+// One 16-row tile of G_dir = Kh_dir I_el (columns of degree < N; columns of
+// degree >= the tile's highest row degree are zero and skipped).
+template <int N, int MTI, bool RES>
+__device__ __forceinline__ d4 kh_tile(const double *Kh_l, const double *Kh_g, const double *Iel, int dir, int li,
+                                      int lk)
+{
+    using Dm = Dim<N>;
+    constexpr int B = Dm::B, B1 = Dm::B1, B1P = Dm::B1P;
+    constexpr int LAST = 16 * MTI + 15 < B - 1 ? 16 * MTI + 15 : B - 1;
+    constexpr int KE = (nb3(deg_of(LAST) - 1) + 3) / 4;
+    const int i = 16 * MTI + li;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KE; ++s) {
+        const int k = 4 * s + lk;
+        double a = 0.0;
+        if (i < B && k < B1) {
+            if constexpr (RES) a = Kh_l[(dir * B + i) * B1P + k];
+            else a = Kh_g[(dir * B + i) * B + k];
+        }
+        const double b = (k < B1 && li < NE) ? Iel[k * NE + li] : 0.0;
+        acc = mfma(a, b, acc);
+    }
+    return acc;
+}
+
 template <int N>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(Dim<N>::T) __attribute__((amdgpu_waves_per_eu(2)))
 k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
     using Dm = Dim<N>;
     constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, BP = Dm::BP, MT1 = Dm::MT1, MTf = Dm::MTf, OT = Dm::OT,
                   TPW = Dm::TPW, QPT = Dm::QPT;
-    constexpr int KS = (B + 3) / 4;
+    constexpr int KS = (B + 3) / 4, THREADS = Dm::T, WAVES = Dm::WV;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double *const D = reinterpret_cast<double *>(lds_raw), *const Dn = D + B * NQ, *const G = Dn + B * NQ,
                  *const Kt_l = G + B1 * NQ;
@@ -121,8 +178,9 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
             Kt_l[dr * BP + k] = Kt_g[(dir * B + (dr - dir * B1)) * B + k];
         }
     }
-    // the next element's Q and star operands travel in registers
-    double qn[QPT], sn[7];
+    // below degree 6 the next element's Q and star operands travel in registers
+    constexpr int PQ = Dm::P_PF ? QPT : 1;
+    double qn[PQ], sn[7];
     VItem it = items ? items[0] : one, nx = it;
     int cur = 0, ncur = 0;
     auto fetch = [&](int64_t gg) {
@@ -130,30 +188,40 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
         const int64_t ee = gg - nx.first;
         const double *Qe = nx.Q + ee * NQ * B;
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) {
+        for (int u = 0; u < PQ; ++u) {
             const int i = tid + u * THREADS;
             qn[u] = i < NQ * B ? Qe[i] : 0.0;
         }
         star_b(nx.star + ee * 3 * NQ * NE, col, lk, sn);
     };
-    if ((int64_t)blockIdx.x < total) fetch(blockIdx.x);
+    if constexpr (Dm::P_PF)
+        if ((int64_t)blockIdx.x < total) fetch(blockIdx.x);
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         while (g >= it.first + it.E) it = items[++cur];
         const int64_t e = g - it.first;
         const double dt = it.dt, w0 = it.omega[0], w1 = it.omega[1], w2 = it.omega[2];
-        __syncthreads();    // the previous element's LDS reads are done (and Kt is staged)
-#pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-            const int i = tid + u * THREADS;
-            if (i < NQ * B) {
-                const int p = i / B, k = i - p * B;
-                D[k * NQ + p] = qn[u];
-            }
-        }
         double sb[7];
+        __syncthreads();    // the previous element's LDS reads are done (and Kt is staged)
+        if constexpr (Dm::P_PF) {
 #pragma unroll
-        for (int s = 0; s < 7; ++s) sb[s] = sn[s];
-        if (g + gridDim.x < total) fetch(g + gridDim.x);
+            for (int u = 0; u < QPT; ++u) {
+                const int i = tid + u * THREADS;
+                if (i < NQ * B) {
+                    const int p = i / B, k = i - p * B;
+                    D[k * NQ + p] = qn[u];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 7; ++s) sb[s] = sn[s];
+            if (g + gridDim.x < total) fetch(g + gridDim.x);
+        } else {
+            const double *Qe = it.Q + e * NQ * B;
+            for (int i = tid; i < NQ * B; i += THREADS) {
+                const int p = i / B, k = i - p * B;
+                D[k * NQ + p] = Qe[i];
+            }
+            star_b(it.star + e * 3 * NQ * NE, col, lk, sb);
+        }
         __syncthreads();
         d4 Is[TPW];
 #pragma unroll
@@ -170,18 +238,13 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
         for (int d = 0; d < N; ++d) {
             // G_dir = Kt_dir D_el over the rows of degree < N
             for (int t = wave; t < 3 * MT1; t += WAVES) {
-                const int dir = t / MT1, mt = t - dir * MT1, i = 16 * mt + li;
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int k = 4 * s + lk;
-                    double a = 0.0;
-                    if (i < B1 && k < B) {
-                        if constexpr (Dm::P_RES) a = Kt_l[(dir * B1 + i) * BP + k];
-                        else a = Kt_g[(dir * B + i) * B + k];
-                    }
-                    const double b = (k < B && li < NE) ? Dc[k * NQ + li] : 0.0;
-                    acc = mfma(a, b, acc);
+                const int dir = t / MT1, mt = t - dir * MT1;
+                d4 acc;
+                switch (mt) {
+                case 0: acc = kt_tile<N, 0, Dm::P_RES>(Kt_l, Kt_g, Dc, dir, li, lk); break;
+                case 1: acc = kt_tile<N, 1, Dm::P_RES>(Kt_l, Kt_g, Dc, dir, li, lk); break;
+                case 2: acc = kt_tile<N, 2, Dm::P_RES>(Kt_l, Kt_g, Dc, dir, li, lk); break;
+                default: acc = kt_tile<N, 3, Dm::P_RES>(Kt_l, Kt_g, Dc, dir, li, lk); break;
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -259,13 +322,13 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
 }
 
 template <int N>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(Dim<N>::T) __attribute__((amdgpu_waves_per_eu(2)))
 k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
     using Dm = Dim<N>;
     constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, B1P = Dm::B1P, BfP = Dm::BfP, WP = Dm::WP, MT = Dm::MT,
                   MTf = Dm::MTf, OT = Dm::OT, TPW = Dm::TPW;
-    constexpr int KS1 = (B1 + 3) / 4, KSF = (Bf + 3) / 4, KSR = (4 * Bf + 3) / 4;
+    constexpr int KSF = (Bf + 3) / 4, KSR = (4 * Bf + 3) / 4, THREADS = Dm::T, WAVES = Dm::WV, QPT = Dm::QPT;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double *const f_l = reinterpret_cast<double *>(lds_raw), *const Iel = f_l + 3 * Bf * BfP,
                  *const G = Iel + B * NE, *const X = G + B * NQ, *const F = X + 4 * Bf * NE,
@@ -284,33 +347,101 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             Kh_l[dr * B1P + (i - dr * B1)] = Kh_g[dr * B + (i - dr * B1)];
         }
     }
-    VItem it = items ? items[0] : one;
-    int cur = 0;
+    // The element's inputs: elastic columns of I, own traces, neighbour
+    // traces (gathered), A+ and A-; below degree 6 those of the next element
+    // are fetched into registers while this one computes.
+    constexpr bool PF = N <= 5;
+    constexpr int PI = PF ? (NE * B + THREADS - 1) / THREADS : 1, PT = PF ? (4 * NE * Bf + THREADS - 1) / THREADS : 1,
+                  PA = PF ? (4 * NQ * NE + THREADS - 1) / THREADS : 1;
+    double ri[PI], rto[PT], rtn[PT], rap[PA], ram[PA];
+    VItem it = items ? items[0] : one, nx = it;
+    int cur = 0, ncur = 0;
+    auto fetch = [&](int64_t gg) {
+        while (gg >= nx.first + nx.E) nx = items[++ncur];
+        const int64_t ee = gg - nx.first;
+        const double *Ig = nx.I + ee * NQ * B, *to = nx.traces + ee * 4 * NE * Bf;
+        const double *ap = nx.Ap + ee * 4 * NQ * NE, *am = nx.Am + ee * 4 * NQ * NE;
+#pragma unroll
+        for (int u = 0; u < PI; ++u) {
+            const int i = tid + u * THREADS;
+            ri[u] = i < NE * B ? Ig[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int i = tid + u * THREADS;
+            rto[u] = i < 4 * NE * Bf ? to[i] : 0.0;
+            double v = 0.0;
+            if (i < 4 * NE * Bf) {
+                const int s = i / (NE * Bf), r = i - s * NE * Bf;
+                const int32_t nu = nx.neigh[ee * 4 + s];
+                if (nu >= 0 && nu < nx.E)
+                    v = nx.traces[((int64_t)nu * 4 + (nx.face_rot[ee * 4 + s] & 3)) * NE * Bf + r];
+            }
+            rtn[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            const int i = tid + u * THREADS;
+            rap[u] = i < 4 * NQ * NE ? ap[i] : 0.0;
+            ram[u] = i < 4 * NQ * NE ? am[i] : 0.0;
+        }
+    };
+    if constexpr (PF)
+        if ((int64_t)blockIdx.x < total) fetch(blockIdx.x);
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         while (g >= it.first + it.E) it = items[++cur];
         const int64_t e = g - it.first;
         const double *Ig = it.I + e * NQ * B;
         __syncthreads();    // the previous element's LDS reads are done (and f, Kh are staged)
-        // stage the element: elastic columns of I, own and neighbour traces, [A+ A-]
-        for (int i = tid; i < NE * B; i += THREADS) {
-            const int p = i / B, k = i - p * B;
-            Iel[k * NE + p] = Ig[i];
-        }
-        const double *to = it.traces + e * 4 * NE * Bf;
-        for (int i = tid; i < 4 * NE * Bf; i += THREADS) To[i] = to[i];
-        for (int i = tid; i < 4 * NE * Bf; i += THREADS) {
-            const int s = i / (NE * Bf), r = i - s * NE * Bf, q = r / Bf, m = r - q * Bf;
-            const int32_t nu = it.neigh[e * 4 + s];
-            double v = 0.0;
-            if (nu >= 0 && nu < it.E)
-                v = it.traces[(((int64_t)nu * 4 + (it.face_rot[e * 4 + s] & 3)) * NE + q) * Bf + m];
-            Tn[(s * NE + q) * BfP + m] = v;
-        }
-        const double *ap = it.Ap + e * 4 * NQ * NE, *am = it.Am + e * 4 * NQ * NE;
-        for (int i = tid; i < 4 * NQ * NE; i += THREADS) {
-            const int sp = i / NE, q = i - sp * NE;
-            W[sp * WP + q] = ap[i];
-            W[sp * WP + NE + q] = am[i];
+        if constexpr (PF) {
+#pragma unroll
+            for (int u = 0; u < PI; ++u) {
+                const int i = tid + u * THREADS;
+                if (i < NE * B) {
+                    const int p = i / B, k = i - p * B;
+                    Iel[k * NE + p] = ri[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const int i = tid + u * THREADS;
+                if (i < 4 * NE * Bf) {
+                    const int sq = i / Bf;
+                    To[i] = rto[u];
+                    Tn[sq * BfP + (i - sq * Bf)] = rtn[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PA; ++u) {
+                const int i = tid + u * THREADS;
+                if (i < 4 * NQ * NE) {
+                    const int sp = i / NE, q = i - sp * NE;
+                    W[sp * WP + q] = rap[u];
+                    W[sp * WP + NE + q] = ram[u];
+                }
+            }
+            if (g + gridDim.x < total) fetch(g + gridDim.x);
+        } else {
+            for (int i = tid; i < NE * B; i += THREADS) {
+                const int p = i / B, k = i - p * B;
+                Iel[k * NE + p] = Ig[i];
+            }
+            const double *to = it.traces + e * 4 * NE * Bf;
+            for (int i = tid; i < 4 * NE * Bf; i += THREADS) To[i] = to[i];
+            for (int i = tid; i < 4 * NE * Bf; i += THREADS) {
+                const int s = i / (NE * Bf), r = i - s * NE * Bf, q = r / Bf, m = r - q * Bf;
+                const int32_t nu = it.neigh[e * 4 + s];
+                double v = 0.0;
+                if (nu >= 0 && nu < it.E)
+                    v = it.traces[(((int64_t)nu * 4 + (it.face_rot[e * 4 + s] & 3)) * NE + q) * Bf + m];
+                Tn[(s * NE + q) * BfP + m] = v;
+            }
+            const double *ap = it.Ap + e * 4 * NQ * NE, *am = it.Am + e * 4 * NQ * NE;
+            for (int i = tid; i < 4 * NQ * NE; i += THREADS) {
+                const int sp = i / NE, q = i - sp * NE;
+                W[sp * WP + q] = ap[i];
+                W[sp * WP + NE + q] = am[i];
+            }
         }
         double sb[7];
         star_b(it.star + e * 3 * NQ * NE, col, lk, sb);
@@ -318,18 +449,15 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
         // phase A: G_dir = Kh_dir I_el (columns of degree < N);  X_s = f^h x_nbr
         for (int t = wave; t < 3 * MT + 4 * MTf; t += WAVES) {
             if (t < 3 * MT) {
-                const int dir = t / MT, mt = t - dir * MT, i = 16 * mt + li;
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < KS1; ++s) {
-                    const int k = 4 * s + lk;
-                    double a = 0.0;
-                    if (i < B && k < B1) {
-                        if constexpr (Dm::C_RES) a = Kh_l[(dir * B + i) * B1P + k];
-                        else a = Kh_g[(dir * B + i) * B + k];
-                    }
-                    const double b = (k < B1 && li < NE) ? Iel[k * NE + li] : 0.0;
-                    acc = mfma(a, b, acc);
+                const int dir = t / MT, mt = t - dir * MT;
+                d4 acc;
+                switch (mt) {
+                case 0: acc = kh_tile<N, 0, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
+                case 1: acc = kh_tile<N, 1, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
+                case 2: acc = kh_tile<N, 2, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
+                case 3: acc = kh_tile<N, 3, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
+                case 4: acc = kh_tile<N, 4, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
+                default: acc = kh_tile<N, 5, Dm::C_RES>(Kh_l, Kh_g, Iel, dir, li, lk); break;
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -357,6 +485,20 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             }
         }
         __syncthreads();
+        // the update's Q and source term E I, loaded now and used after phase C
+        double *const Qe = it.Q + e * NQ * B;
+        double qv[QPT];
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int i = tid + u * THREADS, p = i / B, k = i - p * B;
+            double v = 0.0;
+            if (i < NQ * B) {
+                if (p < 6) v = -(Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
+                else if (p >= 9) v = -(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])) * Ig[i];
+                v += Qe[i];
+            }
+            qv[u] = v;
+        }
         // phase B: volume [G_1 G_2 G_3] [S_1 S_2 S_3]^T into the owned tiles;
         // F_s = [x_own X_s] [A+_s A-_s]^T
         d4 acc[TPW];
@@ -400,7 +542,8 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
         for (int j = 0; j < TPW; ++j) {
             const int t = wave + WAVES * j, mt = t >> 1, i = 16 * mt + li;
             if (t < OT) {
-#pragma unroll
+                // chunks of 7 k-steps keep the loads in flight (and the registers) bounded
+#pragma unroll 7
                 for (int st = 0; st < KSR; ++st) {
                     const int kk = 4 * st + lk, s = kk / Bf, m = kk - s * Bf;
                     const double a = (i < B && kk < 4 * Bf) ? Rh_g[(s * B + i) * Bf + m] : 0.0;
@@ -416,26 +559,23 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
         }
         __syncthreads();
         // Q += volume + fluxes + E I
-        double *Qe = it.Q + e * NQ * B;
-        for (int i = tid; i < NQ * B; i += THREADS) {
-            const int p = i / B, k = i - p * B;
-            double src = 0.0;
-            if (p < 6) src = -(Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
-            else if (p >= 9) src = -(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])) * Ig[i];
-            Qe[i] += G[k * NQ + p] + src;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int i = tid + u * THREADS, p = i / B, k = i - p * B;
+            if (i < NQ * B) Qe[i] = qv[u] + G[k * NQ + p];
         }
     }
 }
 
 template <typename K>
-hipError_t persistent_grid(K kernel, size_t lds, int *grid)
+hipError_t persistent_grid(K kernel, int threads, size_t lds, int *grid)
 {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, THREADS, lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, threads, lds);
     if (e != hipSuccess) return e;
     *grid = cus * (per_cu > 0 ? per_cu : 1);
     return hipSuccess;
@@ -452,8 +592,8 @@ hipError_t prepare()
     using Dm = Dim<N>;
     if (Grid<N>::predict && Grid<N>::correct) return hipSuccess;
     int a = 0, b = 0;
-    hipError_t e = persistent_grid(k_visco_predict<N>, (size_t)Dm::P_LDS * 8, &a);
-    if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, (size_t)Dm::C_LDS * 8, &b);
+    hipError_t e = persistent_grid(k_visco_predict<N>, Dm::T, (size_t)Dm::P_LDS * 8, &a);
+    if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, Dm::T, (size_t)Dm::C_LDS * 8, &b);
     if (e != hipSuccess) return e;
     Grid<N>::predict = a, Grid<N>::correct = b;
     return hipSuccess;
@@ -467,11 +607,11 @@ hipError_t step(const VItem *items, const VItem &one, int64_t total, const doubl
     if (e != hipSuccess) return e;
     const int64_t gp = Grid<N>::predict, gc = Grid<N>::correct;
     const unsigned np = (unsigned)(total < gp ? total : gp), nc = (unsigned)(total < gc ? total : gc);
-    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(THREADS), (size_t)Dm::P_LDS * 8, s, items, one, total,
+    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(Dm::T), (size_t)Dm::P_LDS * 8, s, items, one, total,
                        blob);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(THREADS), (size_t)Dm::C_LDS * 8, s, items, one, total,
+    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(Dm::T), (size_t)Dm::C_LDS * 8, s, items, one, total,
                        blob);
     return hipGetLastError();
 }
