@@ -7,10 +7,12 @@ generated code, Sec. 4.9).  This script asks the library's own host generator
 matrices of every supported degree and writes `dg_generated.h`:
 
   * per-column functors that apply one column of a matrix to register arrays
-    with fully unrolled FMAs, one FMA per non-zero, the matrix entry written
-    as a literal of the kernel's precision.  The compiler materialises FP64
-    literals with scalar moves and folds FP32 literals into the FMA, so the
-    matrices cost neither memory traffic nor scalar-cache latency.
+    with fully unrolled FMAs, one FMA per non-zero.  FP32 kernels take the
+    matrix entry as a literal, which the compiler folds into the FMA.  FP64
+    kernels read it from a per-degree constant table in consumption order:
+    an FP64 literal costs two scalar moves of 12 bytes each, while table
+    entries arrive eight at a time through one scalar load, which shrinks
+    the code and its scalar issue.
 
 Column order conventions (matching the consumption order of the kernels):
   KtCol<N,L>    acc[k] += Kt^d[k][L] * x_d           (predictor, d = 0..2)
@@ -59,10 +61,18 @@ def matrices(lib, N):
                 Rh=take((4, B, Bf)), f=take((3, Bf, Bf)))
 
 
-def _lit(v):
-    """A matrix entry as a typed literal: real(...) rounds once, at compile
-    time, to the precision of the kernel."""
-    return "real(%r)" % float(v)
+class Consts:
+    """The FP64 entries of one degree in the order the code consumes them."""
+
+    def __init__(self, N):
+        self.N = N
+        self.values = []
+
+    def __call__(self, v):
+        """A matrix entry: the table entry in FP64 kernels, a literal of the
+        kernel's precision (rounded once, at compile time) otherwise."""
+        self.values.append(float(v))
+        return "dg_kv<real>(dg_kc_%d[%d], %r)" % (self.N, len(self.values) - 1, float(v))
 
 
 class Emitter:
@@ -73,10 +83,12 @@ class Emitter:
         self.lines.append(s)
 
 
-# A scheduling fence after every FENCE FMAs of a functor.  Each FP64 literal is
-# materialised by two scalar moves; without fences the scheduler hoists the
-# moves of a whole row block, overflows the SGPRs and spills them into VGPR
-# lanes (readlane/writelane), which costs more VGPRs than the accumulators.
+# A scheduling fence after every FENCE FMAs of a functor, in FP32 code only.
+# The fences date from FP64 literals, each materialised by two scalar moves:
+# without them the scheduler hoisted the moves of a whole row block,
+# overflowed the SGPRs and spilled them into VGPR lanes.  With the FP64 table
+# the loads may run ahead freely (1-3 % faster at degrees 5 and 6 without
+# fences); the FP32 kernels keep the schedule they were tuned with.
 FENCE = 16
 
 
@@ -85,7 +97,7 @@ def fenced(stms):
     for i, s in enumerate(stms):
         out.append(s)
         if (i + 1) % FENCE == 0 and i + 1 < len(stms):
-            out.append("__builtin_amdgcn_sched_barrier(0);")
+            out.append("if constexpr (sizeof(real) == 4) __builtin_amdgcn_sched_barrier(0);")
     return out
 
 
@@ -113,9 +125,11 @@ def check_structure(N, M):
             raise RuntimeError("Khat has non-zeros beyond the degree N-1 columns")
 
 
-def gen_degree(em, N, M):
+def gen_degree(out, N, M):
     check_structure(N, M)
     B, Bf = M["B"], M["Bf"]
+    em = Emitter()
+    _lit = Consts(N)
     # K-tilde, column(L)-major, then d, then k
     for key, nm in (("Kt", "KtCol"), ("Kh", "KhCol")):
         A = M[key]
@@ -187,6 +201,12 @@ def gen_degree(em, N, M):
                 for j, v in terms[1:]:
                     em(f"  out[{i}] = fma({_lit(v)}, in[{j}], out[{i}]);")
             em("} };")
+    # the degree's FP64 table first, then its functors
+    out(f"static __constant__ double dg_kc_{N}[{len(_lit.values)}] = {{")
+    for i in range(0, len(_lit.values), 4):
+        out("  " + ", ".join("%r" % v for v in _lit.values[i:i + 4]) + ",")
+    out("};")
+    out.lines.extend(em.lines)
 
 
 def flop_counts(M, N):
@@ -212,6 +232,9 @@ def generate(host_lib_path, out_path):
     em("template <int N, int S, int M> struct RhCol;")
     em("template <int N, int H> struct FApply;")
     em("template <int N, int H, int D> struct FBlock;")
+    em("// a matrix entry: from the constant table in FP64, as the literal otherwise")
+    em("template <typename real> __device__ __forceinline__ real dg_kv(const double &table, double lit)")
+    em("{ if constexpr (sizeof(real) == 8) return table; else return real(lit); }")
     stats = {}
     for N in DEGREES:
         M = matrices(lib, N)
