@@ -29,6 +29,11 @@
 // k-steps of its zero block.  These reference matrices stay resident in LDS
 // for the workgroup's lifetime where two workgroups per CU still fit;
 // otherwise the tiles read them from the (L2-resident) blob.
+// The workgroup clears its LDS once.  Operand arrays carry zero rows and
+// columns up to whole k-steps, and are ordered so that a tile's reads past
+// its matrix land in other LDS arrays (or, for the blob, in the next matrix):
+// those values only reach output rows or columns that are never stored, so
+// the inner loops carry no bounds selects.
 // Layouts: Q, I [E][27][B]; star [E][3][27][9]; Aplus, Aminus [E][4][27][9];
 // traces [E][4][9][Bf]; the reference blob as dg_reference_matrices writes it.
 #include <hip/hip_runtime.h>
@@ -57,28 +62,29 @@ __host__ __device__ constexpr int deg_of(int r)
 template <int N>
 struct Dim {
     static constexpr int B = nb3(N), Bf = nb2(N), B1 = nb3(N - 1);
-    // odd row strides of the LDS matrices read 16 rows at a time (no bank conflicts)
-    static constexpr int BP = B | 1, B1P = B1 | 1, BfP = Bf | 1, WP = 19;
+    static constexpr int BK = (B + 3) / 4 * 4;             // rows of the derivative arrays (zero beyond B)
+    // odd row strides of the LDS matrices read 16 rows at a time (no bank
+    // conflicts); B1P also covers whole k-steps (zero columns beyond B1)
+    static constexpr int BP = B | 1, B1P = ((B1 + 3) / 4 * 4) | 1, BfP = Bf | 1, WP = 19, TP = 21, PAD = 32;
     static constexpr int MT = (B + 15) / 16, MT1 = (B1 + 15) / 16, MTf = (Bf + 15) / 16;
     // workgroup: 4 waves, 8 at degree 6 (whose LDS admits one workgroup per CU)
-    static constexpr int T = N == 6 ? 512 : 256, WV = T / 64;
+    static constexpr int T = N == 6 ? 512 : 256, WV = T / 64, MINW = 2;
     static constexpr int OT = 2 * MT;                      // 16 x 16 tiles of a [B][27] array
     static constexpr int TPW = (OT + WV - 1) / WV;         // of them owned per wave
     static constexpr int QPT = (NQ * B + T - 1) / T;
     // the predictor prefetches the next element into registers below degree 6
     // (at degree 6 the registers go to two waves per SIMD instead)
     static constexpr bool P_PF = N <= 5;
-    // predictor LDS (doubles): D, Dn [B][27], G [B1][27]; Kt rows of degree < N [3][B1][BP] if resident
-    static constexpr int P_EL = 2 * B * NQ + B1 * NQ, P_KT = 3 * B1 * BP;
+    // predictor LDS (doubles): [Kt rows of degree < N [3][B1][BP] if resident] D, Dn [BK][27], G [B1][27], pad
+    static constexpr int P_EL = 2 * BK * NQ + B1 * NQ + PAD, P_KT = 3 * B1 * BP;
     // resident where two workgroups per CU fit; at degree 6 (one wave per
     // SIMD for its registers anyway) resident in the whole LDS
     static constexpr bool P_RES = 8 * (P_EL + P_KT) <= (N == 6 ? 160 * 1024 : LDS_TWO_PER_CU);
     static constexpr int P_LDS = P_EL + (P_RES ? P_KT : 0);
-    // corrector LDS: f [3][Bf][BfP], I_el [B][9], G [B][27], X [4 Bf][9], F [4 Bf][27],
-    // own traces [4][9][Bf], neighbour traces [4][9][BfP], [A+ A-] [4][27][WP];
-    // Kh columns of degree < N [3][B][B1P] if resident
-    static constexpr int C_EL = 3 * Bf * BfP + B * NE + B * NQ + 4 * Bf * NE + 4 * Bf * NQ + 4 * NE * Bf +
-                                4 * NE * BfP + 4 * NQ * WP;
+    // corrector LDS: [Kh columns of degree < N [3][B][B1P] if resident] f [3][Bf][BfP], neighbour traces
+    // [4][9][Bf], [A+ A-] [4][27][WP], I_el [B][9], G [B][27], [x_own X] [4 Bf][TP], F [4 Bf][27], pad
+    static constexpr int C_EL = 3 * Bf * BfP + 4 * NE * Bf + 4 * NQ * WP + B * NE + B * NQ + 4 * Bf * TP +
+                                4 * Bf * NQ + PAD;
     static constexpr int C_KH = 3 * B * B1P;
     static constexpr bool C_RES = 8 * (C_EL + C_KH) <= LDS_TWO_PER_CU;
     static constexpr int C_LDS = C_EL + (C_RES ? C_KH : 0);
@@ -115,19 +121,17 @@ __device__ __forceinline__ d4 kt_tile(const double *Kt_l, const double *Kt_g, co
                                       int lk)
 {
     using Dm = Dim<N>;
-    constexpr int B = Dm::B, B1 = Dm::B1, BP = Dm::BP, KS = (B + 3) / 4, KS0 = nb3(deg_of(16 * MTI)) / 4;
+    constexpr int B = Dm::B, B1 = Dm::B1, BP = Dm::BP, KS = Dm::BK / 4, KS0 = nb3(deg_of(16 * MTI)) / 4;
+    // rows past B1 and columns past 9 are never stored; rows of Dc past B are zero
     const int i = 16 * MTI + li;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = KS0; s < KS; ++s) {
         const int k = 4 * s + lk;
-        double a = 0.0;
-        if (i < B1 && k < B) {
-            if constexpr (RES) a = Kt_l[(dir * B1 + i) * BP + k];
-            else a = Kt_g[(dir * B + i) * B + k];
-        }
-        const double b = (k < B && li < NE) ? Dc[k * NQ + li] : 0.0;
-        acc = mfma(a, b, acc);
+        double a;
+        if constexpr (RES) a = Kt_l[(dir * B1 + i) * BP + k];
+        else a = Kt_g[(dir * B + i) * B + k];
+        acc = mfma(a, Dc[k * NQ + li], acc);
     }
     return acc;
 }
@@ -142,18 +146,17 @@ __device__ __forceinline__ d4 kh_tile(const double *Kh_l, const double *Kh_g, co
     constexpr int B = Dm::B, B1 = Dm::B1, B1P = Dm::B1P;
     constexpr int LAST = 16 * MTI + 15 < B - 1 ? 16 * MTI + 15 : B - 1;
     constexpr int KE = (nb3(deg_of(LAST) - 1) + 3) / 4;
+    // columns of Kh past B1 are zero (padding in LDS, true zeros in the
+    // blob); rows past B and columns past 9 are never stored
     const int i = 16 * MTI + li;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < KE; ++s) {
         const int k = 4 * s + lk;
-        double a = 0.0;
-        if (i < B && k < B1) {
-            if constexpr (RES) a = Kh_l[(dir * B + i) * B1P + k];
-            else a = Kh_g[(dir * B + i) * B + k];
-        }
-        const double b = (k < B1 && li < NE) ? Iel[k * NE + li] : 0.0;
-        acc = mfma(a, b, acc);
+        double a;
+        if constexpr (RES) a = Kh_l[(dir * B + i) * B1P + k];
+        else a = Kh_g[(dir * B + i) * B + k];
+        acc = mfma(a, Iel[k * NE + li], acc);
     }
     return acc;
 }
@@ -165,13 +168,16 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
     using Dm = Dim<N>;
     constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, BP = Dm::BP, MT1 = Dm::MT1, MTf = Dm::MTf, OT = Dm::OT,
                   TPW = Dm::TPW, QPT = Dm::QPT;
-    constexpr int KS = (B + 3) / 4, THREADS = Dm::T, WAVES = Dm::WV;
+    constexpr int BK = Dm::BK, KS = BK / 4, THREADS = Dm::T, WAVES = Dm::WV;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *const D = reinterpret_cast<double *>(lds_raw), *const Dn = D + B * NQ, *const G = Dn + B * NQ,
-                 *const Kt_l = G + B1 * NQ;
+    double *const base = reinterpret_cast<double *>(lds_raw);
+    double *const Kt_l = base, *const D = base + (Dm::P_RES ? Dm::P_KT : 0), *const Dn = D + BK * NQ,
+                 *const G = Dn + BK * NQ;
     const double *Kt_g = blob + 3 * B * B, *R_g = blob + 6 * B * B;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int col = 16 * (wave & 1) + li;    // every tile a wave owns is in column block wave & 1
+    for (int i = tid; i < Dm::P_LDS; i += THREADS) base[i] = 0.0;
+    __syncthreads();
     if constexpr (Dm::P_RES) {
         for (int i = tid; i < 3 * B1 * B; i += THREADS) {
             const int dr = i / B, k = i - dr * B, dir = dr / B1;
@@ -305,12 +311,12 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
         for (int t = wave; t < 4 * MTf; t += WAVES) {
             const int s = t / MTf, mt = t - s * MTf, i = 16 * mt + li;
             d4 acc = {0.0, 0.0, 0.0, 0.0};
+            // rows past Bf read on into the next face's rows (or R-hat) and are
+            // never stored; rows of Dx past B are zero
 #pragma unroll
             for (int st = 0; st < KS; ++st) {
                 const int k = 4 * st + lk;
-                const double a = (i < Bf && k < B) ? R_g[(s * B + k) * Bf + i] : 0.0;
-                const double b = (k < B && li < NE) ? Dx[k * NQ + li] : 0.0;
-                acc = mfma(a, b, acc);
+                acc = mfma(R_g[(s * B + k) * Bf + i], Dx[k * NQ + li], acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -326,17 +332,19 @@ __global__ void __launch_bounds__(Dim<N>::T) __attribute__((amdgpu_waves_per_eu(
 k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
     using Dm = Dim<N>;
-    constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, B1P = Dm::B1P, BfP = Dm::BfP, WP = Dm::WP, MT = Dm::MT,
-                  MTf = Dm::MTf, OT = Dm::OT, TPW = Dm::TPW;
-    constexpr int KSF = (Bf + 3) / 4, KSR = (4 * Bf + 3) / 4, THREADS = Dm::T, WAVES = Dm::WV, QPT = Dm::QPT;
+    constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, B1P = Dm::B1P, BfP = Dm::BfP, WP = Dm::WP, TP = Dm::TP,
+                  MT = Dm::MT, MTf = Dm::MTf, OT = Dm::OT, TPW = Dm::TPW;
+    constexpr int KSF = (Bf + 3) / 4, KSR = Bf, THREADS = Dm::T, WAVES = Dm::WV, QPT = Dm::QPT;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *const f_l = reinterpret_cast<double *>(lds_raw), *const Iel = f_l + 3 * Bf * BfP,
-                 *const G = Iel + B * NE, *const X = G + B * NQ, *const F = X + 4 * Bf * NE,
-                 *const To = F + 4 * Bf * NQ, *const Tn = To + 4 * NE * Bf, *const W = Tn + 4 * NE * BfP,
-                 *const Kh_l = W + 4 * NQ * WP;
+    double *const base = reinterpret_cast<double *>(lds_raw);
+    double *const Kh_l = base, *const f_l = base + (Dm::C_RES ? Dm::C_KH : 0), *const Tn = f_l + 3 * Bf * BfP,
+                 *const W = Tn + 4 * NE * Bf, *const Iel = W + 4 * NQ * WP, *const G = Iel + B * NE,
+                 *const T = G + B * NQ, *const F = T + 4 * Bf * TP;
     const double *Kh_g = blob, *Rh_g = blob + 6 * B * B + 4 * B * Bf, *f_g = Rh_g + 4 * B * Bf;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int col = 16 * (wave & 1) + li;    // every owned output tile is in column block wave & 1
+    for (int i = tid; i < Dm::C_LDS; i += THREADS) base[i] = 0.0;
+    __syncthreads();
     for (int i = tid; i < 3 * Bf * Bf; i += THREADS) {
         const int r = i / Bf;
         f_l[r * BfP + (i - r * Bf)] = f_g[i];
@@ -348,9 +356,11 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
         }
     }
     // The element's inputs: elastic columns of I, own traces, neighbour
-    // traces (gathered), A+ and A-; below degree 6 those of the next element
-    // are fetched into registers while this one computes.
-    constexpr bool PF = N <= 5;
+    // traces (gathered), A+ and A-; at degrees 2, 3 and 5 those of the next
+    // element are fetched into registers while this one computes (at degree 4
+    // the registers would spill at two waves per SIMD, at degree 6 they go to
+    // the eight waves of the workgroup).
+    constexpr bool PF = N <= 5 && N != 4;
     constexpr int PI = PF ? (NE * B + THREADS - 1) / THREADS : 1, PT = PF ? (4 * NE * Bf + THREADS - 1) / THREADS : 1,
                   PA = PF ? (4 * NQ * NE + THREADS - 1) / THREADS : 1;
     double ri[PI], rto[PT], rtn[PT], rap[PA], ram[PA];
@@ -406,9 +416,9 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             for (int u = 0; u < PT; ++u) {
                 const int i = tid + u * THREADS;
                 if (i < 4 * NE * Bf) {
-                    const int sq = i / Bf;
-                    To[i] = rto[u];
-                    Tn[sq * BfP + (i - sq * Bf)] = rtn[u];
+                    const int s = i / (NE * Bf), r = i - s * NE * Bf, q = r / Bf, m = r - q * Bf;
+                    T[(s * Bf + m) * TP + q] = rto[u];
+                    Tn[i] = rtn[u];
                 }
             }
 #pragma unroll
@@ -427,14 +437,14 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
                 Iel[k * NE + p] = Ig[i];
             }
             const double *to = it.traces + e * 4 * NE * Bf;
-            for (int i = tid; i < 4 * NE * Bf; i += THREADS) To[i] = to[i];
             for (int i = tid; i < 4 * NE * Bf; i += THREADS) {
                 const int s = i / (NE * Bf), r = i - s * NE * Bf, q = r / Bf, m = r - q * Bf;
+                T[(s * Bf + m) * TP + q] = to[i];
                 const int32_t nu = it.neigh[e * 4 + s];
                 double v = 0.0;
                 if (nu >= 0 && nu < it.E)
-                    v = it.traces[(((int64_t)nu * 4 + (it.face_rot[e * 4 + s] & 3)) * NE + q) * Bf + m];
-                Tn[(s * NE + q) * BfP + m] = v;
+                    v = it.traces[((int64_t)nu * 4 + (it.face_rot[e * 4 + s] & 3)) * NE * Bf + r];
+                Tn[i] = v;
             }
             const double *ap = it.Ap + e * 4 * NQ * NE, *am = it.Am + e * 4 * NQ * NE;
             for (int i = tid; i < 4 * NQ * NE; i += THREADS) {
@@ -470,17 +480,17 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
                 // that the read stays inside the matrix
                 const int h0 = (it.face_rot[e * 4 + s] >> 2) & 3, h = h0 > 2 ? 0 : h0;
                 d4 acc = {0.0, 0.0, 0.0, 0.0};
+                // rows past Bf and columns past 9 are never stored; the k-step
+                // past Bf meets the zero of the select
 #pragma unroll
                 for (int st = 0; st < KSF; ++st) {
                     const int k = 4 * st + lk;
-                    const double a = (i < Bf && k < Bf) ? f_l[(h * Bf + i) * BfP + k] : 0.0;
-                    const double b = (k < Bf && li < NE) ? Tn[(s * NE + li) * BfP + k] : 0.0;
-                    acc = mfma(a, b, acc);
+                    acc = mfma(f_l[(h * Bf + i) * BfP + k], k < Bf ? Tn[(s * NE + li) * Bf + k] : 0.0, acc);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * mt + lk + 4 * r;
-                    if (row < Bf && li < NE) X[(s * Bf + row) * NE + li] = acc[r];
+                    if (row < Bf && li < NE) T[(s * Bf + row) * TP + NE + li] = acc[r];
                 }
             }
         }
@@ -510,7 +520,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
 #pragma unroll
                 for (int s = 0; s < 7; ++s) {
                     const int k = 4 * s + lk;
-                    acc[j] = mfma((i < B && k < NQ) ? G[i * NQ + k] : 0.0, sb[s], acc[j]);
+                    acc[j] = mfma(G[i * NQ + k], sb[s], acc[j]);   // rows past B never stored; sb is 0 past k = 26
                 }
             }
         }
@@ -518,16 +528,11 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             const int s = t / (2 * MTf), r2 = t - s * 2 * MTf, mt = r2 >> 1;
             const int i = 16 * mt + li, fc = 16 * (r2 & 1) + li;
             d4 f = {0.0, 0.0, 0.0, 0.0};
+            // columns 18-20 of T are zero; rows past Bf and columns past 27 are never stored
 #pragma unroll
             for (int st = 0; st < 5; ++st) {
                 const int k = 4 * st + lk;
-                double a = 0.0;
-                if (i < Bf) {
-                    if (k < NE) a = To[(s * NE + k) * Bf + i];
-                    else if (k < 2 * NE) a = X[(s * Bf + i) * NE + (k - NE)];
-                }
-                const double b = (fc < NQ && k < 2 * NE) ? W[(s * NQ + fc) * WP + k] : 0.0;
-                f = mfma(a, b, f);
+                f = mfma(T[(s * Bf + i) * TP + k], W[(s * NQ + fc) * WP + k], f);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -546,9 +551,8 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
 #pragma unroll 7
                 for (int st = 0; st < KSR; ++st) {
                     const int kk = 4 * st + lk, s = kk / Bf, m = kk - s * Bf;
-                    const double a = (i < B && kk < 4 * Bf) ? Rh_g[(s * B + i) * Bf + m] : 0.0;
-                    const double b = (kk < 4 * Bf && col < NQ) ? F[kk * NQ + col] : 0.0;
-                    acc[j] = mfma(a, b, acc[j]);
+                    // rows past B read on into the next face's rows (or f) and are never stored
+                    acc[j] = mfma(Rh_g[(s * B + i) * Bf + m], F[kk * NQ + col], acc[j]);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
