@@ -53,6 +53,8 @@ def parse():
                          "lina: the LinA ADER-DG-SEM scheme on cuboids (Sec. 5.2)")
     ap.add_argument("--grading", type=float, default=64.0, help="lts: cell-width ratio across the graded mesh")
     ap.add_argument("--meshes", type=int, default=32)
+    ap.add_argument("--fusion", choices=["auto", "on", "off"], default="auto",
+                    help="single: the plan's step schedule (auto), one fused launch per step (on) or two (off)")
     ap.add_argument("--elastic-only", action="store_true", help="batched: no viscoelastic meshes")
     ap.add_argument("--rate", type=float, default=5.0, help="serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=16)
@@ -690,6 +692,8 @@ def main():
     N = args.degree
     prec = {"fp64": dg.DG_FP64, "fp32": dg.DG_FP32, "mixed": dg.DG_MIXED, "bf16x3": dg.DG_BF16X3}[args.precision]
     plan = dg.Plan(N, prec)
+    if args.fusion != "auto":
+        plan.set_fusion(args.fusion == "on")
     seed = seed_for(1)
     log("building mesh n=%d degree=%d" % (args.n, N))
     mesh = cube_mesh(args.n, seed)
