@@ -194,6 +194,12 @@ def batched(args):
         del star, Ap, Am
     total = sum(m["E"] for m in meshes)
     log("batch of %d meshes, %d elements, degrees %s" % (len(meshes), total, sorted(set(degrees.tolist()))))
+    # the viscoelastic launch shapes (waves per workgroup, workgroups per CU)
+    # picked by the library's tuner before the batch records its graph
+    shapes = {int(m["degree"]): None for m in meshes if m.get("n_quant") == 27}
+    for N in sorted(shapes):
+        shapes[N] = dg.visco_tune(N, 20000)
+        log("viscoelastic degree %d: %d waves per workgroup, %d workgroups per CU" % (N, *shapes[N]))
     batch = dg.Batch(prec, meshes)
     torch.cuda.synchronize()
     batch.step(args.warmup)
@@ -215,7 +221,8 @@ def batched(args):
                                   "elements per mesh, degrees uniform in 2..6, one HIP graph replay per step"
                                   % (len(meshes), kinds.count("visco"), total),
                       "elements": total, "degrees": degrees.tolist(), "mesh_elements": [m["E"] for m in meshes],
-                      "models": kinds},
+                      "models": kinds,
+                      "visco_shapes": {str(N): {"waves": w, "groups_per_cu": g} for N, (w, g) in shapes.items()}},
            "useful_gflops": flops * args.steps / el / 1e9, "roofline": roof}
     batch.close()
     print(json.dumps(out), flush=True)

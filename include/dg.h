@@ -379,6 +379,20 @@ int dg_lina_coefficients(int order, double rho0, double K0, double h, double *ou
 int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, double dt, void *Q, void *sides,
                  const double *coef, const int32_t *neigh, hipStream_t stream);
 
+/* Launch-shape tuner of the viscoelastic kernels (the batched form's tiles
+ * and elements per workgroup).  Both kernels keep one element per workgroup
+ * in flight and walk the work list with persistent workgroups; the shape is
+ * the number of waves per workgroup (4 or 8: how an element's 16x16 tiles are
+ * spread) and the number of resident workgroups per CU (elements in flight
+ * per CU, up to what LDS and registers admit).  Times every candidate for
+ * `degree` on E synthetic elements (allocates and frees device memory, and
+ * synchronizes `stream`) and keeps the fastest for the process: later
+ * dg_visco_step calls, and batches created or updated afterwards, use it.
+ * The shape never changes an element's arithmetic (results are bitwise the
+ * same).  waves / groups_per_cu (may be null) receive the choice.
+ * E in [64, 2^22]. */
+int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *waves, int *groups_per_cu);
+
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 
 /* One mesh of a batch.  All pointers are device pointers owned by the caller

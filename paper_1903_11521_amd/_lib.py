@@ -90,6 +90,7 @@ def _load():
         lib.dg_lina_coefficients.argtypes = [i32, dbl, dbl, dbl, dp]
         lib.dg_lina_step.argtypes = [i32, i32, i64, i32, dbl, vp, vp, vp, vp, vp]
         lib.dg_visco_step.argtypes = [i32, i64, dbl, i32, vp, vp, vp, vp, vp, vp, dp, vp, vp, vp, vp]
+        lib.dg_visco_tune.argtypes = [i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = lib
         return lib
 
@@ -606,6 +607,15 @@ def visco_step(degree, Q, I, traces, star, Aplus, Aminus, omega, ref, neigh, fac
     _check(_load().dg_visco_step(int(degree), E, float(dt), int(n_steps), *args, _dptr(om), refp,
                                  t(None, neigh, (E, 4), torch.int32, "neigh"),
                                  t(None, face_rot, (E, 4), torch.uint8, "face_rot"), Plan._stream(stream)))
+
+
+def visco_tune(degree, E=20000, stream=None):
+    """dg_visco_tune: time the viscoelastic launch shapes of `degree` on E
+    synthetic elements and keep the fastest for the process; returns
+    (waves per workgroup, resident workgroups per CU)."""
+    w, g = ctypes.c_int(), ctypes.c_int()
+    _check(_load().dg_visco_tune(int(degree), int(E), Plan._stream(stream), ctypes.byref(w), ctypes.byref(g)))
+    return w.value, g.value
 
 
 # ---------------------------------------------------------------------------

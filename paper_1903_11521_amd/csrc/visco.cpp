@@ -5,8 +5,10 @@
 
 #include <cmath>
 #include <cstdio>
+#include <vector>
 
 #include "dg_internal.h"
+#include "refmat.h"
 #include "visco_internal.h"
 
 extern "C" int dg_visco_step(int degree, int64_t E, double dt, int n_steps, double *Q, double *I, double *traces,
@@ -43,5 +45,102 @@ extern "C" int dg_visco_step(int degree, int64_t E, double dt, int n_steps, doub
             return dg_set_error(DG_EHIP, buf);
         }
     }
+    return DG_OK;
+}
+
+namespace {
+
+// device buffers of the tuning run, freed on every return path
+struct TuneMem {
+    std::vector<void *> p;
+    void *get(size_t bytes)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return q;
+    }
+    ~TuneMem()
+    {
+        for (void *q : p) (void)hipFree(q);
+    }
+};
+
+int tune_fail(hipError_t e)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "dg_visco_tune: HIP error %d (%s)", (int)e, hipGetErrorString(e));
+    return dg_set_error(DG_EHIP, buf);
+}
+
+}  // namespace
+
+extern "C" int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *waves, int *groups_per_cu)
+{
+    char buf[256];
+    if (degree < 2 || degree > 6) {
+        std::snprintf(buf, sizeof buf, "dg_visco_tune: degree %d outside 2..6", degree);
+        return dg_set_error(DG_EUNSUPPORTED, buf);
+    }
+    if (E < 64 || E > ((int64_t)1 << 22)) return dg_set_error(DG_EINVAL, "dg_visco_tune: tuning size outside [64, 2^22]");
+    const int64_t B = dgref::basis_size(degree), Bf = dgref::face_basis_size(degree);
+    TuneMem m;
+    double *Q = (double *)m.get((size_t)E * 27 * B * 8), *I = (double *)m.get((size_t)E * 27 * B * 8);
+    double *tr = (double *)m.get((size_t)E * 36 * Bf * 8), *star = (double *)m.get((size_t)E * 3 * 27 * 9 * 8);
+    double *Ap = (double *)m.get((size_t)E * 4 * 27 * 9 * 8), *Am = (double *)m.get((size_t)E * 4 * 27 * 9 * 8);
+    int32_t *neigh = (int32_t *)m.get((size_t)E * 16);
+    uint8_t *rot = (uint8_t *)m.get((size_t)E * 4);
+    const size_t nblob = dgref::blob_size(degree);
+    double *blob = (double *)m.get(nblob * 8);
+    if (!Q || !I || !tr || !star || !Ap || !Am || !neigh || !rot || !blob)
+        return dg_set_error(DG_ENOMEM, "dg_visco_tune: out of device memory");
+    // zero data (the kernels' time does not depend on the values), the
+    // product's reference matrices, and neighbours 1, 7, E/64 and E/8 away
+    std::vector<double> hb(nblob);
+    if (dgref::build(degree, hb.data()) != 0) return dg_set_error(DG_EINVAL, "dg_visco_tune: reference matrices");
+    std::vector<int32_t> nb((size_t)E * 4);
+    const int64_t off[4] = {1, 7, E / 64 + 1, E / 8 + 1};
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) nb[(size_t)(e * 4 + f)] = (int32_t)((e + off[f]) % E);
+    hipError_t e = hipMemcpyAsync(blob, hb.data(), nblob * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(neigh, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, stream);
+    for (auto z : {std::make_pair((void *)Q, (size_t)E * 27 * B * 8), std::make_pair((void *)I, (size_t)E * 27 * B * 8),
+                   std::make_pair((void *)tr, (size_t)E * 36 * Bf * 8),
+                   std::make_pair((void *)star, (size_t)E * 3 * 27 * 9 * 8),
+                   std::make_pair((void *)Ap, (size_t)E * 4 * 27 * 9 * 8),
+                   std::make_pair((void *)Am, (size_t)E * 4 * 27 * 9 * 8), std::make_pair((void *)rot, (size_t)E * 4)})
+        if (e == hipSuccess) e = hipMemsetAsync(z.first, 0, z.second, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return tune_fail(e);
+    VItem one{};
+    one.E = E, one.first = 0, one.dt = 1e-3;
+    one.Q = Q, one.I = I, one.traces = tr, one.star = star, one.Ap = Ap, one.Am = Am, one.neigh = neigh;
+    one.face_rot = rot;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    VShape best{0, 0};
+    float best_ms = 0.0f;
+    for (int w : {4, 8}) {
+        int maxpc = 0;
+        if (e == hipSuccess) e = visco_prepare_shape(degree, w, &maxpc);
+        for (int pc = 1; e == hipSuccess && pc <= maxpc; ++pc) {
+            const VShape sh{w, pc};
+            e = visco_step_shape(degree, sh, nullptr, 1, one, E, blob, stream);    // warm-up
+            if (e == hipSuccess) e = hipEventRecord(t0, stream);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = visco_step_shape(degree, sh, nullptr, 1, one, E, blob, stream);
+            if (e == hipSuccess) e = hipEventRecord(t1, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess && (best.waves == 0 || ms < best_ms)) best = sh, best_ms = ms;
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return tune_fail(e);
+    visco_set_shape(degree, best);
+    if (waves) *waves = best.waves;
+    if (groups_per_cu) *groups_per_cu = best.per_cu;
     return DG_OK;
 }

@@ -26,6 +26,23 @@ struct VItem {
 hipError_t visco_step_launch(int degree, const VItem *items, int n_items, const VItem &one, int64_t total,
                              const double *blob, hipStream_t s);
 
-// Sets the kernels' LDS limits and persistent grid sizes for a degree (done
-// by the first launch otherwise; call before recording launches into a graph).
+// Launch shape of a degree: waves per workgroup (4 or 8) and resident
+// workgroups per CU of the persistent grids (0: as many as fit).  Process-wide,
+// set by dg_visco_tune; the default is 4 waves (8 at degree 6), all that fit.
+struct VShape {
+    int waves;
+    int per_cu;
+};
+VShape visco_shape(int degree);
+void visco_set_shape(int degree, VShape shape);
+
+// Sets the kernels' LDS limits and reads their occupancy for a degree and
+// wave count (done by the first launch otherwise; call before recording
+// launches into a graph).  max_per_cu (may be null): the larger of the two
+// kernels' resident workgroups per CU.
+hipError_t visco_prepare_shape(int degree, int waves, int *max_per_cu);
 hipError_t visco_prepare(int degree);
+
+// visco_step_launch with an explicit shape.
+hipError_t visco_step_shape(int degree, VShape shape, const VItem *items, int n_items, const VItem &one,
+                            int64_t total, const double *blob, hipStream_t s);

@@ -59,7 +59,7 @@ __host__ __device__ constexpr int deg_of(int r)
     return d;
 }
 
-template <int N>
+template <int N, int WVv = (N == 6 ? 8 : 4)>
 struct Dim {
     static constexpr int B = nb3(N), Bf = nb2(N), B1 = nb3(N - 1);
     static constexpr int BK = (B + 3) / 4 * 4;             // rows of the derivative arrays (zero beyond B)
@@ -67,8 +67,9 @@ struct Dim {
     // conflicts); B1P also covers whole k-steps (zero columns beyond B1)
     static constexpr int BP = B | 1, B1P = ((B1 + 3) / 4 * 4) | 1, BfP = Bf | 1, WP = 19, TP = 21, PAD = 32;
     static constexpr int MT = (B + 15) / 16, MT1 = (B1 + 15) / 16, MTf = (Bf + 15) / 16;
-    // workgroup: 4 waves, 8 at degree 6 (whose LDS admits one workgroup per CU)
-    static constexpr int T = N == 6 ? 512 : 256, WV = T / 64, MINW = 2;
+    // workgroup of WVv waves (by default 4, and 8 at degree 6, whose LDS
+    // admits one workgroup per CU; dg_visco_tune may pick the other)
+    static constexpr int T = 64 * WVv, WV = WVv, MINW = 2;
     static constexpr int OT = 2 * MT;                      // 16 x 16 tiles of a [B][27] array
     static constexpr int TPW = (OT + WV - 1) / WV;         // of them owned per wave
     static constexpr int QPT = (NQ * B + T - 1) / T;
@@ -161,11 +162,11 @@ __device__ __forceinline__ d4 kh_tile(const double *Kh_l, const double *Kh_g, co
     return acc;
 }
 
-template <int N>
-__global__ void __launch_bounds__(Dim<N>::T) __attribute__((amdgpu_waves_per_eu(2)))
+template <int N, int WVv>
+__global__ void __launch_bounds__(64 * WVv) __attribute__((amdgpu_waves_per_eu(2)))
 k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
-    using Dm = Dim<N>;
+    using Dm = Dim<N, WVv>;
     constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, BP = Dm::BP, MT1 = Dm::MT1, MTf = Dm::MTf, OT = Dm::OT,
                   TPW = Dm::TPW, QPT = Dm::QPT;
     constexpr int BK = Dm::BK, KS = BK / 4, THREADS = Dm::T, WAVES = Dm::WV;
@@ -327,11 +328,11 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
     }
 }
 
-template <int N>
-__global__ void __launch_bounds__(Dim<N>::T) __attribute__((amdgpu_waves_per_eu(2)))
+template <int N, int WVv>
+__global__ void __launch_bounds__(64 * WVv) __attribute__((amdgpu_waves_per_eu(2)))
 k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const double *__restrict__ blob)
 {
-    using Dm = Dim<N>;
+    using Dm = Dim<N, WVv>;
     constexpr int B = Dm::B, Bf = Dm::Bf, B1 = Dm::B1, B1P = Dm::B1P, BfP = Dm::BfP, WP = Dm::WP, TP = Dm::TP,
                   MT = Dm::MT, MTf = Dm::MTf, OT = Dm::OT, TPW = Dm::TPW;
     constexpr int KSF = (Bf + 3) / 4, KSR = Bf, THREADS = Dm::T, WAVES = Dm::WV, QPT = Dm::QPT;
@@ -572,64 +573,109 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
 }
 
 template <typename K>
-hipError_t persistent_grid(K kernel, int threads, size_t lds, int *grid)
+hipError_t occupancy(K kernel, int threads, size_t lds, int *per_cu)
 {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, threads, lds);
-    if (e != hipSuccess) return e;
-    *grid = cus * (per_cu > 0 ? per_cu : 1);
-    return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void *)kernel, threads, lds);
+    if (e == hipSuccess && *per_cu < 1) *per_cu = 1;
+    return e;
 }
 
-template <int N>
-struct Grid {
-    static inline int predict = 0, correct = 0;    // CUs x resident workgroups, set once
+template <int N, int WVv>
+struct Occ {
+    static inline int cus = 0, predict = 0, correct = 0;    // CUs and resident workgroups per CU, set once
 };
 
-template <int N>
+template <int N, int WVv>
 hipError_t prepare()
 {
-    using Dm = Dim<N>;
-    if (Grid<N>::predict && Grid<N>::correct) return hipSuccess;
-    int a = 0, b = 0;
-    hipError_t e = persistent_grid(k_visco_predict<N>, Dm::T, (size_t)Dm::P_LDS * 8, &a);
-    if (e == hipSuccess) e = persistent_grid(k_visco_correct<N>, Dm::T, (size_t)Dm::C_LDS * 8, &b);
+    using Dm = Dim<N, WVv>;
+    using O = Occ<N, WVv>;
+    if (O::cus) return hipSuccess;
+    int dev = 0, cus = 0, a = 0, b = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = occupancy(k_visco_predict<N, WVv>, Dm::T, (size_t)Dm::P_LDS * 8, &a);
+    if (e == hipSuccess) e = occupancy(k_visco_correct<N, WVv>, Dm::T, (size_t)Dm::C_LDS * 8, &b);
     if (e != hipSuccess) return e;
-    Grid<N>::predict = a, Grid<N>::correct = b;
+    O::predict = a, O::correct = b, O::cus = cus;
     return hipSuccess;
 }
 
-template <int N>
-hipError_t step(const VItem *items, const VItem &one, int64_t total, const double *blob, hipStream_t s)
+// One step over the work list: persistent grids of CUs x min(per_cu, the
+// resident limit) workgroups (per_cu 0: the resident limit).
+template <int N, int WVv>
+hipError_t step(const VItem *items, const VItem &one, int64_t total, const double *blob, int per_cu, hipStream_t s)
 {
-    using Dm = Dim<N>;
-    hipError_t e = prepare<N>();
+    using Dm = Dim<N, WVv>;
+    using O = Occ<N, WVv>;
+    hipError_t e = prepare<N, WVv>();
     if (e != hipSuccess) return e;
-    const int64_t gp = Grid<N>::predict, gc = Grid<N>::correct;
+    const int64_t gp = (int64_t)O::cus * (per_cu > 0 && per_cu < O::predict ? per_cu : O::predict);
+    const int64_t gc = (int64_t)O::cus * (per_cu > 0 && per_cu < O::correct ? per_cu : O::correct);
     const unsigned np = (unsigned)(total < gp ? total : gp), nc = (unsigned)(total < gc ? total : gc);
-    hipLaunchKernelGGL(k_visco_predict<N>, dim3(np), dim3(Dm::T), (size_t)Dm::P_LDS * 8, s, items, one, total,
-                       blob);
+    hipLaunchKernelGGL((k_visco_predict<N, WVv>), dim3(np), dim3(Dm::T), (size_t)Dm::P_LDS * 8, s, items, one,
+                       total, blob);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_visco_correct<N>, dim3(nc), dim3(Dm::T), (size_t)Dm::C_LDS * 8, s, items, one, total,
-                       blob);
+    hipLaunchKernelGGL((k_visco_correct<N, WVv>), dim3(nc), dim3(Dm::T), (size_t)Dm::C_LDS * 8, s, items, one,
+                       total, blob);
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t step_shape(int waves, const VItem *items, const VItem &one, int64_t total, const double *blob,
+                      int per_cu, hipStream_t s)
+{
+    return waves == 8 ? step<N, 8>(items, one, total, blob, per_cu, s) : step<N, 4>(items, one, total, blob, per_cu, s);
+}
+
+template <int N>
+hipError_t prepare_shape(int waves, int *max_per_cu)
+{
+    hipError_t e = waves == 8 ? prepare<N, 8>() : prepare<N, 4>();
+    if (e == hipSuccess && max_per_cu)
+        *max_per_cu = waves == 8 ? (Occ<N, 8>::predict > Occ<N, 8>::correct ? Occ<N, 8>::predict : Occ<N, 8>::correct)
+                                 : (Occ<N, 4>::predict > Occ<N, 4>::correct ? Occ<N, 4>::predict : Occ<N, 4>::correct);
+    return e;
+}
+
+// the launch shape of each degree (process-wide): waves per workgroup, resident workgroups per CU (0: all that fit)
+VShape g_shape[7] = {{4, 0}, {4, 0}, {4, 0}, {4, 0}, {4, 0}, {4, 0}, {8, 0}};
+
 }  // namespace dgv
 
-hipError_t visco_prepare(int degree)
+VShape visco_shape(int degree) { return degree >= 2 && degree <= 6 ? dgv::g_shape[degree] : VShape{4, 0}; }
+
+void visco_set_shape(int degree, VShape shape)
+{
+    if (degree >= 2 && degree <= 6) dgv::g_shape[degree] = shape;
+}
+
+hipError_t visco_prepare_shape(int degree, int waves, int *max_per_cu)
 {
     switch (degree) {
-    case 2: return dgv::prepare<2>();
-    case 3: return dgv::prepare<3>();
-    case 4: return dgv::prepare<4>();
-    case 5: return dgv::prepare<5>();
-    case 6: return dgv::prepare<6>();
+    case 2: return dgv::prepare_shape<2>(waves, max_per_cu);
+    case 3: return dgv::prepare_shape<3>(waves, max_per_cu);
+    case 4: return dgv::prepare_shape<4>(waves, max_per_cu);
+    case 5: return dgv::prepare_shape<5>(waves, max_per_cu);
+    case 6: return dgv::prepare_shape<6>(waves, max_per_cu);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t visco_prepare(int degree) { return visco_prepare_shape(degree, visco_shape(degree).waves, nullptr); }
+
+hipError_t visco_step_shape(int degree, VShape shape, const VItem *items, int n_items, const VItem &one,
+                            int64_t total, const double *blob, hipStream_t s)
+{
+    if (total <= 0 || n_items <= 0) return hipSuccess;
+    switch (degree) {
+    case 2: return dgv::step_shape<2>(shape.waves, items, one, total, blob, shape.per_cu, s);
+    case 3: return dgv::step_shape<3>(shape.waves, items, one, total, blob, shape.per_cu, s);
+    case 4: return dgv::step_shape<4>(shape.waves, items, one, total, blob, shape.per_cu, s);
+    case 5: return dgv::step_shape<5>(shape.waves, items, one, total, blob, shape.per_cu, s);
+    case 6: return dgv::step_shape<6>(shape.waves, items, one, total, blob, shape.per_cu, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -637,13 +683,5 @@ hipError_t visco_prepare(int degree)
 hipError_t visco_step_launch(int degree, const VItem *items, int n_items, const VItem &one, int64_t total,
                              const double *blob, hipStream_t s)
 {
-    if (total <= 0 || n_items <= 0) return hipSuccess;
-    switch (degree) {
-    case 2: return dgv::step<2>(items, one, total, blob, s);
-    case 3: return dgv::step<3>(items, one, total, blob, s);
-    case 4: return dgv::step<4>(items, one, total, blob, s);
-    case 5: return dgv::step<5>(items, one, total, blob, s);
-    case 6: return dgv::step<6>(items, one, total, blob, s);
-    default: return hipErrorInvalidValue;
-    }
+    return visco_step_shape(degree, visco_shape(degree), items, n_items, one, total, blob, s);
 }

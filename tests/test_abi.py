@@ -225,3 +225,15 @@ def test_batch_item_argument_errors():
     arr = (L.BatchItem * 1)(item(27, (1.0, float("nan"), 2.0)))
     assert lib.dg_batch_create(0, arr, 1, ctypes.byref(out)) == -1 and b"relaxation" in lib.dg_last_error()
     assert not out.value
+
+
+def test_visco_tune_argument_errors():
+    """Rejected before anything touches the device."""
+    import ctypes
+    import paper_1903_11521_amd._lib as L
+    lib = L._load()
+    w, g = ctypes.c_int(), ctypes.c_int()
+    assert lib.dg_visco_tune(7, 1000, None, ctypes.byref(w), ctypes.byref(g)) == -2
+    assert b"degree" in lib.dg_last_error()
+    assert lib.dg_visco_tune(5, 10, None, ctypes.byref(w), ctypes.byref(g)) == -1
+    assert b"tuning size" in lib.dg_last_error()

@@ -140,3 +140,20 @@ def test_visco_meshes_in_a_mixed_batch():
     torch.cuda.synchronize()
     assert torch.equal(Qa, el["Q"])
     batch.close()
+
+
+def test_visco_tune_keeps_results_bitwise():
+    """The tuner picks a launch shape per degree; the step's results do not
+    depend on it."""
+    _say("test_visco_tune_keeps_results_bitwise")
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd._lib import DGError
+    N = 4
+    case = _case(N, 3, 51)
+    before = _gpu(N, *case, 2)
+    waves, per_cu = dg.visco_tune(N, 3000)
+    assert waves in (4, 8) and per_cu >= 1
+    after = _gpu(N, *case, 2)
+    assert np.array_equal(before, after)
+    with pytest.raises(DGError):
+        dg.visco_tune(9, 3000)
