@@ -198,7 +198,7 @@ def batched(args):
     # picked by the library's tuner before the batch records its graph
     shapes = {int(m["degree"]): None for m in meshes if m.get("n_quant") == 27}
     for N in sorted(shapes):
-        shapes[N] = dg.visco_tune(N, 20000)
+        shapes[N] = dg.visco_tune(N, 100000)
         log("viscoelastic degree %d: %d waves per workgroup, %d workgroups per CU" % (N, *shapes[N]))
     batch = dg.Batch(prec, meshes)
     torch.cuda.synchronize()
@@ -522,6 +522,7 @@ def visco(args):
     rows = []
     for N in sorted({3, args.degree}):
         B, Bf = comb(N + 3, 3), comb(N + 2, 2)
+        waves, per_cu = dg.visco_tune(N, 100000)
         ref = torch.from_numpy(dg.reference_blob(N)).to(dev)
         Q = torch.randn((E, 27, B), generator=g, dtype=torch.float64, device=dev)
         I = torch.empty_like(Q)
@@ -537,7 +538,8 @@ def visco(args):
         el = e0.elapsed_time(e1) / 1e3 / steps
         flops, nbytes = visco_model(N)
         roof = pm.kernel_roofline(flops * E, nbytes * E, el, "f64")
-        rows.append({"degree": N, "elements": E, "ms_per_step": el * 1e3, "element_updates_per_s": E / el,
+        rows.append({"degree": N, "elements": E, "waves_per_workgroup": waves, "workgroups_per_cu": per_cu,
+                     "ms_per_step": el * 1e3, "element_updates_per_s": E / el,
                      "useful_gflops": flops * E / el / 1e9, "flops_per_element": flops,
                      "bytes_per_element": nbytes, "bound": roof["bound"], "frac": roof["frac"]})
         log("visco degree %d, %d elements: %.3f ms/step, %.2f M element-updates/s, %.0f GFLOP/s (%s, %.3f)"

@@ -609,7 +609,7 @@ def visco_step(degree, Q, I, traces, star, Aplus, Aminus, omega, ref, neigh, fac
                                  t(None, face_rot, (E, 4), torch.uint8, "face_rot"), Plan._stream(stream)))
 
 
-def visco_tune(degree, E=20000, stream=None):
+def visco_tune(degree, E=100_000, stream=None):
     """dg_visco_tune: time the viscoelastic launch shapes of `degree` on E
     synthetic elements and keep the fastest for the process; returns
     (waves per workgroup, resident workgroups per CU)."""
