@@ -392,6 +392,13 @@ int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, doub
  * same).  waves / groups_per_cu (may be null) receive the choice.
  * E in [64, 2^22]. */
 int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *waves, int *groups_per_cu);
+/* Sets the launch shape of a degree without timing (for example one saved
+ * from an earlier dg_visco_tune): waves 4 or 8, groups_per_cu 0 (as many as
+ * fit) or a cap in [1, 64] (capped again at what fits).  Host only; later
+ * steps and batches created or updated afterwards use it. */
+int dg_visco_set_shape(int degree, int waves, int groups_per_cu);
+/* The current launch shape of a degree (waves, groups_per_cu may be null). */
+int dg_visco_get_shape(int degree, int *waves, int *groups_per_cu);
 
 /* ---- batches of independent meshes (mixed degrees) --------------------- */
 

@@ -91,6 +91,8 @@ def _load():
         lib.dg_lina_step.argtypes = [i32, i32, i64, i32, dbl, vp, vp, vp, vp, vp]
         lib.dg_visco_step.argtypes = [i32, i64, dbl, i32, vp, vp, vp, vp, vp, vp, dp, vp, vp, vp, vp]
         lib.dg_visco_tune.argtypes = [i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.dg_visco_set_shape.argtypes = [i32, i32, i32]
+        lib.dg_visco_get_shape.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = lib
         return lib
 
@@ -607,6 +609,18 @@ def visco_step(degree, Q, I, traces, star, Aplus, Aminus, omega, ref, neigh, fac
     _check(_load().dg_visco_step(int(degree), E, float(dt), int(n_steps), *args, _dptr(om), refp,
                                  t(None, neigh, (E, 4), torch.int32, "neigh"),
                                  t(None, face_rot, (E, 4), torch.uint8, "face_rot"), Plan._stream(stream)))
+
+
+def visco_shape(degree, shape=None):
+    """The viscoelastic launch shape of a degree, (waves per workgroup,
+    workgroups per CU, 0 = all that fit); with `shape` given, set it first
+    (dg_visco_set_shape)."""
+    lib = _load()
+    if shape is not None:
+        _check(lib.dg_visco_set_shape(int(degree), int(shape[0]), int(shape[1])))
+    w, g = ctypes.c_int(), ctypes.c_int()
+    _check(lib.dg_visco_get_shape(int(degree), ctypes.byref(w), ctypes.byref(g)))
+    return w.value, g.value
 
 
 def visco_tune(degree, E=100_000, stream=None):

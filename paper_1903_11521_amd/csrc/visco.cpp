@@ -144,3 +144,22 @@ extern "C" int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *wav
     if (groups_per_cu) *groups_per_cu = best.per_cu;
     return DG_OK;
 }
+
+extern "C" int dg_visco_set_shape(int degree, int waves, int groups_per_cu)
+{
+    if (degree < 2 || degree > 6) return dg_set_error(DG_EUNSUPPORTED, "dg_visco_set_shape: degree outside 2..6");
+    if (waves != 4 && waves != 8) return dg_set_error(DG_EINVAL, "dg_visco_set_shape: waves must be 4 or 8");
+    if (groups_per_cu < 0 || groups_per_cu > 64)
+        return dg_set_error(DG_EINVAL, "dg_visco_set_shape: workgroups per CU outside [0, 64]");
+    visco_set_shape(degree, VShape{waves, groups_per_cu});
+    return DG_OK;
+}
+
+extern "C" int dg_visco_get_shape(int degree, int *waves, int *groups_per_cu)
+{
+    if (degree < 2 || degree > 6) return dg_set_error(DG_EUNSUPPORTED, "dg_visco_get_shape: degree outside 2..6");
+    const VShape sh = visco_shape(degree);
+    if (waves) *waves = sh.waves;
+    if (groups_per_cu) *groups_per_cu = sh.per_cu;
+    return DG_OK;
+}

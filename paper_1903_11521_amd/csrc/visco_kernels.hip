@@ -42,6 +42,11 @@
 #include "dg_common.h"
 #include "visco_internal.h"
 
+// No implicit contraction: every multiply-add below is an explicit fma, so
+// all launch shapes (template instantiations) round alike and give the same
+// bits.
+#pragma clang fp contract(off)
+
 namespace dgv {
 
 using dgk::nb2;
@@ -96,12 +101,12 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// (E x)[p] for the structured source matrix, x a row of 27 values
-__device__ __forceinline__ double source(const double *x, int p, double w0, double w1, double w2)
+// a + (E x)[p] for the structured source matrix, x a row of 27 values
+__device__ __forceinline__ double add_source(double a, const double *x, int p, double w0, double w1, double w2)
 {
-    if (p < 6) return -(x[9 + p] + x[15 + p] + x[21 + p]);
-    if (p < 9) return 0.0;
-    return -(p < 15 ? w0 : (p < 21 ? w1 : w2)) * x[p];
+    if (p < 6) return a - (x[9 + p] + x[15 + p] + x[21 + p]);
+    if (p < 9) return a;
+    return fma(-(p < 15 ? w0 : (p < 21 ? w1 : w2)), x[p], a);
 }
 
 // the star matrices as the B operand [S_1 S_2 S_3]^T: row k = 9 dir + q,
@@ -279,9 +284,9 @@ k_visco_predict(const VItem *__restrict__ items, VItem one, int64_t total, const
                     for (int r = 0; r < 4; ++r) {
                         const int row = 16 * mt + lk + 4 * r;
                         if (row < B && col < NQ) {
-                            const double v = acc[r] + source(Dc + row * NQ, col, w0, w1, w2);
+                            const double v = add_source(acc[r], Dc + row * NQ, col, w0, w1, w2);
                             Dx[row * NQ + col] = v;
-                            Is[j][r] += c * v;
+                            Is[j][r] = fma(c, v, Is[j][r]);
                         }
                     }
                 }
@@ -504,9 +509,9 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             const int i = tid + u * THREADS, p = i / B, k = i - p * B;
             double v = 0.0;
             if (i < NQ * B) {
-                if (p < 6) v = -(Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
-                else if (p >= 9) v = -(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])) * Ig[i];
-                v += Qe[i];
+                if (p < 6) v = Qe[i] - (Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
+                else if (p < 9) v = Qe[i];
+                else v = fma(-(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])), Ig[i], Qe[i]);
             }
             qv[u] = v;
         }

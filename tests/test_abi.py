@@ -237,3 +237,17 @@ def test_visco_tune_argument_errors():
     assert b"degree" in lib.dg_last_error()
     assert lib.dg_visco_tune(5, 10, None, ctypes.byref(w), ctypes.byref(g)) == -1
     assert b"tuning size" in lib.dg_last_error()
+
+
+def test_visco_shape_set_and_get():
+    """Host-only launch-shape table of the viscoelastic kernels."""
+    import paper_1903_11521_amd as dg
+    from paper_1903_11521_amd._lib import DGError
+    old = dg.visco_shape(3)
+    assert dg.visco_shape(3, (8, 2)) == (8, 2)
+    assert dg.visco_shape(3, old) == old
+    for bad in ((6, 0), (4, -1), (4, 65)):
+        with pytest.raises(DGError):
+            dg.visco_shape(3, bad)
+    with pytest.raises(DGError):
+        dg.visco_shape(7)

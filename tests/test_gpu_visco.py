@@ -157,3 +157,61 @@ def test_visco_tune_keeps_results_bitwise():
     assert np.array_equal(before, after)
     with pytest.raises(DGError):
         dg.visco_tune(9, 3000)
+
+
+@pytest.mark.parametrize("N,n", [(3, 8), (5, 6), (6, 4)])
+def test_visco_many_elements_per_workgroup(N, n):
+    """Work lists several times the persistent grid (3072, 1296 and 384
+    elements; the grid has CUs x resident workgroups), so every workgroup
+    walks several elements and runs the prefetch of the next one: one step
+    against the oracle."""
+    _say(f"test_visco_many_elements_per_workgroup N={N} n={n}")
+    case = _case(N, n, 60 + N)
+    got = _gpu(N, *case, 1)
+    ref = _oracle(N, *case, 1)
+    Q = case[-1]
+    assert_close(got - Q, ref - Q, 1e-12, "viscoelastic step increment, %d elements" % case[0].E)
+
+
+def test_visco_batch_of_one_degree_walks_item_boundaries():
+    """Three degree-3 viscoelastic meshes in one batch (162, 1296 and 384
+    elements): one work list whose workgroups cross item boundaries; each
+    mesh equals dg_visco_step alone bitwise, and the largest the oracle."""
+    _say("test_visco_batch_of_one_degree_walks_item_boundaries")
+    import paper_1903_11521_amd as dg
+    items, cases = [], []
+    for n, seed in ((3, 71), (6, 72), (4, 73)):
+        it, c = _visco_mesh(dg, 3, n, seed)
+        items.append(it)
+        cases.append(c)
+    batch = dg.Batch(dg.DG_FP64, items)
+    batch.step(2)
+    torch.cuda.synchronize()
+    for it, c in zip(items, cases):
+        alone = _gpu(3, *c, 2)
+        assert np.array_equal(it["Q"].cpu().numpy(), alone), "mesh of %d elements" % c[0].E
+    ref = _oracle(3, *cases[1], 2)
+    Q = cases[1][-1]
+    assert_close(items[1]["Q"].cpu().numpy() - Q, ref - Q, 1e-12, "batched mesh of 1296 elements")
+    batch.close()
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_visco_every_launch_shape_bitwise(N):
+    """Both wave counts, one workgroup per CU and all that fit: the same
+    bits (the 27x element data of a 1296-element mesh, two steps)."""
+    _say(f"test_visco_every_launch_shape_bitwise N={N}")
+    import paper_1903_11521_amd as dg
+    case = _case(N, 6, 80 + N)
+    keep = dg.visco_shape(N)
+    try:
+        runs = []
+        for shape in ((4, 0), (4, 1), (8, 0), (8, 1)):
+            dg.visco_shape(N, shape)
+            runs.append(_gpu(N, *case, 2))
+    finally:
+        dg.visco_shape(N, keep)
+    shapes = ((4, 0), (4, 1), (8, 0), (8, 1))
+    bad = [(sh, float(np.abs(r - runs[0]).max()), int((r != runs[0]).sum())) for sh, r in zip(shapes[1:], runs[1:])
+           if not np.array_equal(runs[0], r)]
+    assert not bad, "shapes differing from (4, 0): %s" % bad
