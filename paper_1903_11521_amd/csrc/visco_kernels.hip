@@ -120,6 +120,31 @@ __device__ __forceinline__ void star_b(const double *Se, int col, int lk, double
     }
 }
 
+template <int M>
+struct Vals {
+    double v[M];
+};
+
+// Q + (E I) of the update, for the entries i = tid + u T of an element's [27][B] block
+template <int B, int QPT, int T>
+__device__ __forceinline__ Vals<QPT> update_operands(const double *Qe, const double *Ig, double w0, double w1,
+                                                    double w2, int tid)
+{
+    Vals<QPT> r;
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int i = tid + u * T, p = i / B, k = i - p * B;
+        double v = 0.0;
+        if (i < NQ * B) {
+            if (p < 6) v = Qe[i] - (Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
+            else if (p < 9) v = Qe[i];
+            else v = fma(-(p < 15 ? w0 : (p < 21 ? w1 : w2)), Ig[i], Qe[i]);
+        }
+        r.v[u] = v;
+    }
+    return r;
+}
+
 // One 16-row tile of G_dir = Kt_dir D_el (rows of degree < N; columns of
 // degree <= the tile's lowest row degree are zero and skipped).
 template <int N, int MTI, bool RES>
@@ -369,7 +394,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
     constexpr bool PF = N <= 5 && N != 4;
     constexpr int PI = PF ? (NE * B + THREADS - 1) / THREADS : 1, PT = PF ? (4 * NE * Bf + THREADS - 1) / THREADS : 1,
                   PA = PF ? (4 * NQ * NE + THREADS - 1) / THREADS : 1;
-    double ri[PI], rto[PT], rtn[PT], rap[PA], ram[PA];
+    double ri[PI], rto[PT], rtn[PT], rap[PA], ram[PA], sn[7];
     VItem it = items ? items[0] : one, nx = it;
     int cur = 0, ncur = 0;
     auto fetch = [&](int64_t gg) {
@@ -401,6 +426,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             rap[u] = i < 4 * NQ * NE ? ap[i] : 0.0;
             ram[u] = i < 4 * NQ * NE ? am[i] : 0.0;
         }
+        star_b(nx.star + ee * 3 * NQ * NE, col, lk, sn);
     };
     if constexpr (PF)
         if ((int64_t)blockIdx.x < total) fetch(blockIdx.x);
@@ -408,6 +434,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
         while (g >= it.first + it.E) it = items[++cur];
         const int64_t e = g - it.first;
         const double *Ig = it.I + e * NQ * B;
+        double sb[7];
         __syncthreads();    // the previous element's LDS reads are done (and f, Kh are staged)
         if constexpr (PF) {
 #pragma unroll
@@ -436,8 +463,11 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
                     W[sp * WP + NE + q] = ram[u];
                 }
             }
+#pragma unroll
+            for (int s = 0; s < 7; ++s) sb[s] = sn[s];
             if (g + gridDim.x < total) fetch(g + gridDim.x);
         } else {
+            star_b(it.star + e * 3 * NQ * NE, col, lk, sb);
             for (int i = tid; i < NE * B; i += THREADS) {
                 const int p = i / B, k = i - p * B;
                 Iel[k * NE + p] = Ig[i];
@@ -459,8 +489,14 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
                 W[sp * WP + NE + q] = am[i];
             }
         }
-        double sb[7];
-        star_b(it.star + e * 3 * NQ * NE, col, lk, sb);
+        // the update's Q and source term E I: loaded before phase A where the
+        // next element is prefetched (the latency hides behind phases A to C;
+        // at degrees 4 and 6 the longer live range costs more than it hides),
+        // else before phase B; used after phase C
+        double *const Qe = it.Q + e * NQ * B;
+        const double w0 = it.omega[0], w1 = it.omega[1], w2 = it.omega[2];
+        Vals<QPT> qv;
+        if constexpr (PF) qv = update_operands<B, QPT, THREADS>(Qe, Ig, w0, w1, w2, tid);
         __syncthreads();
         // phase A: G_dir = Kh_dir I_el (columns of degree < N);  X_s = f^h x_nbr
         for (int t = wave; t < 3 * MT + 4 * MTf; t += WAVES) {
@@ -501,20 +537,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
             }
         }
         __syncthreads();
-        // the update's Q and source term E I, loaded now and used after phase C
-        double *const Qe = it.Q + e * NQ * B;
-        double qv[QPT];
-#pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-            const int i = tid + u * THREADS, p = i / B, k = i - p * B;
-            double v = 0.0;
-            if (i < NQ * B) {
-                if (p < 6) v = Qe[i] - (Ig[(9 + p) * B + k] + Ig[(15 + p) * B + k] + Ig[(21 + p) * B + k]);
-                else if (p < 9) v = Qe[i];
-                else v = fma(-(p < 15 ? it.omega[0] : (p < 21 ? it.omega[1] : it.omega[2])), Ig[i], Qe[i]);
-            }
-            qv[u] = v;
-        }
+        if constexpr (!PF) qv = update_operands<B, QPT, THREADS>(Qe, Ig, w0, w1, w2, tid);
         // phase B: volume [G_1 G_2 G_3] [S_1 S_2 S_3]^T into the owned tiles;
         // F_s = [x_own X_s] [A+_s A-_s]^T
         d4 acc[TPW];
@@ -572,7 +595,7 @@ k_visco_correct(const VItem *__restrict__ items, VItem one, int64_t total, const
 #pragma unroll
         for (int u = 0; u < QPT; ++u) {
             const int i = tid + u * THREADS, p = i / B, k = i - p * B;
-            if (i < NQ * B) Qe[i] = qv[u] + G[k * NQ + p];
+            if (i < NQ * B) Qe[i] = qv.v[u] + G[k * NQ + p];
         }
     }
 }
