@@ -340,8 +340,13 @@ int dg_lts_destroy(dg_lts *lts);
  * I), star [E][3][27][9], Aplus, Aminus [E][4][27][9] (from
  * dg_visco_element_data_host), ref the blob of dg_reference_matrices for
  * the degree copied to the device, neigh [E][4] (indices outside [0, E): no
- * neighbour), face_rot [E][4] = j | h << 2; omega [3] a HOST array of the
- * relaxation frequencies.  Degrees 2..6. */
+ * neighbour), face_rot [E][4] = j | h << 2 (orientations above 2 are invalid
+ * and read as 0); omega [3] a HOST array of the relaxation frequencies.
+ * Degrees 2..6.  Persistent workgroups walk the elements in the launch shape
+ * of the degree (dg_visco_tune, dg_visco_set_shape).  Errors, before
+ * anything is enqueued: DG_EUNSUPPORTED for the degree; DG_EINVAL for E
+ * outside [0, 2^31), a negative step count, a null pointer, a negative or
+ * non-finite omega or a non-finite dt; DG_EHIP if a launch fails. */
 int dg_visco_step(int degree, int64_t E, double dt, int n_steps, double *Q, double *I, double *traces,
                   const double *star, const double *Aplus, const double *Aminus, const double *omega,
                   const double *ref, const int32_t *neigh, const uint8_t *face_rot, hipStream_t stream);
@@ -390,7 +395,10 @@ int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, doub
  * dg_visco_step calls, and batches created or updated afterwards, use it.
  * The shape never changes an element's arithmetic (results are bitwise the
  * same).  waves / groups_per_cu (may be null) receive the choice.
- * E in [64, 2^22]. */
+ * E in [64, 2^22] (the device memory it needs grows with E and the degree:
+ * about 46 KB per element at degree 6; DG_ENOMEM if it does not fit).  The
+ * shape table is process-wide and not synchronised: tune or set shapes
+ * before other threads launch viscoelastic steps. */
 int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *waves, int *groups_per_cu);
 /* Sets the launch shape of a degree without timing (for example one saved
  * from an earlier dg_visco_tune): waves 4 or 8, groups_per_cu 0 (as many as
