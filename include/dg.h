@@ -396,7 +396,7 @@ int dg_lina_step(dg_precision precision, int order, int64_t E, int n_steps, doub
  * The shape never changes an element's arithmetic (results are bitwise the
  * same).  waves / groups_per_cu (may be null) receive the choice.
  * E in [64, 2^22] (the device memory it needs grows with E and the degree:
- * about 46 KB per element at degree 6; DG_ENOMEM if it does not fit).  The
+ * about 66 KB per element at degree 6; DG_ENOMEM if it does not fit).  The
  * shape table is process-wide and not synchronised: tune or set shapes
  * before other threads launch viscoelastic steps. */
 int dg_visco_tune(int degree, int64_t E, hipStream_t stream, int *waves, int *groups_per_cu);
