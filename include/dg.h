@@ -185,7 +185,10 @@ int dg_pack_star(const dg_plan *plan, int64_t E, const double *star_dense, void 
 int dg_predictor(const dg_plan *plan, int64_t E, double dt, const void *Q, const void *star_packed,
                  void *T, hipStream_t stream);
 
-/* Eq. seissol:timeint: I = sum_d dt/(d+1) T^d, accumulated in FP64. */
+/* Eq. seissol:timeint: I = sum_d dt/(d+1) T^d, accumulated in FP64.  T is
+ * the Taylor-scaled derivative array of dg_predictor; rows of T^d at and past
+ * C(N-d+3, 3) (the staircase, zero for every derivative of the predictor)
+ * are not read. */
 int dg_time_integral(const dg_plan *plan, int64_t E, double dt, const void *T, void *I,
                      hipStream_t stream);
 
