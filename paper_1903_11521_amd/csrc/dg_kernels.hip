@@ -493,17 +493,6 @@ __device__ __forceinline__ void face_trace(const real *I, real *tr)
 }
 
 template <int N, typename real>
-__device__ __forceinline__ void face_trace_rt(int j, const real *I, real *tr)
-{
-    switch (j) {
-    case 0: face_trace<N, 0>(I, tr); break;
-    case 1: face_trace<N, 1>(I, tr); break;
-    case 2: face_trace<N, 2>(I, tr); break;
-    default: face_trace<N, 3>(I, tr); break;
-    }
-}
-
-template <int N, typename real>
 __device__ __forceinline__ void orient_rt(int h, const real *in, real *out)
 {
     if (h == 0) FApply<N, 0>::apply(in, out);
@@ -646,6 +635,23 @@ __global__ void __launch_bounds__(64) k_volume(int64_t E, const real *__restrict
     add_to_q<B>(L, Q, acc, E);
 }
 
+// tr += R^S^T rows [L0, L0+CNT) of a column staged in LDS (col[r] is row
+// L0 + r), in ascending row order as face_trace.  In FP64 the chunk is one
+// code block of its own: this keeps the per-stage flux kernels at two waves
+// per SIMD (by the compiler's resource report), where eight-row blocks or no
+// block boundary at all need more registers.
+template <int N, int S, int L0, int CNT, typename real>
+__device__ __forceinline__ void trace_rows(const real *col, real *tr)
+{
+    if (code_block<real>()) {
+        static_for<0, CNT>([&](auto rj) {
+            constexpr int r = decltype(rj)::value;
+            RCol<N, S, L0 + r>::apply(col[r], tr);
+        });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Local flux: Q += sum_S Rh^S (R^S^T I) A+^S^T   (per-stage form: the trace
 // of each face is accumulated from I rows streamed through LDS)
 template <int N, bool MIX, typename real>
@@ -668,7 +674,7 @@ __global__ void __launch_bounds__(64) k_local_flux(int64_t E, const real *__rest
             constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
             chunk_load<cnt, B>(L, iblk, l0);
             lds_sync();
-            static_for<0, cnt>([&](auto ri) { RCol<N, S, l0 + decltype(ri)::value>::apply(L.own[ri], tr); });
+            trace_rows<N, S, l0, cnt>(L.own, tr);
             lds_sync();
         });
         flux_lift<N, S, MIX>(L, Ap + (L.elem * 4 + S) * 81, acc, [&](auto m0c, auto cntc) {
@@ -698,18 +704,34 @@ __global__ void __launch_bounds__(64) k_neighbour_flux(int64_t E, int64_t nI, co
         }
     }
     lds_sync();
-    real In[B], acc[B], tr[Bf], t2[Bf];
+    real acc[B], tr[Bf], t2[Bf];
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = real(0);
     static_for<0, 4>([&](auto si) {
         constexpr int S = decltype(si)::value;
-        load_columns<B, B>(L, [&](int g) -> const real * {
-            const int nu = nbt[g][S];
-            return nu >= 0 ? I + (int64_t)nu * NQ * B : nullptr;
-        }, In);
         const int nu = nbt[L.e][S];
         const uint8_t fr = face_rot[L.elem * 4 + S];
-        face_trace_rt<N>(fr & 3, In, tr);   // In is zero when there is no neighbour
+        const int j = fr & 3;
+        // the neighbour's I streams through LDS in row chunks (zero rows when
+        // there is no neighbour) and its face-j trace is accumulated per chunk
+#pragma unroll
+        for (int m = 0; m < Bf; ++m) tr[m] = real(0);
+        static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
+            constexpr int l0 = decltype(ci)::value * CH<real>;
+            constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
+            chunk_load<cnt, B>(L, [&](int g) -> const real * {
+                const int n = nbt[g][S];
+                return n >= 0 ? I + (int64_t)n * NQ * B : nullptr;
+            }, l0);
+            lds_sync();
+            switch (j) {
+            case 0: trace_rows<N, 0, l0, cnt>(L.own, tr); break;
+            case 1: trace_rows<N, 1, l0, cnt>(L.own, tr); break;
+            case 2: trace_rows<N, 2, l0, cnt>(L.own, tr); break;
+            default: trace_rows<N, 3, l0, cnt>(L.own, tr); break;
+            }
+            lds_sync();
+        });
         orient_rt<N>(fr >> 2, tr, t2);
         if (nu < 0) {
 #pragma unroll
