@@ -540,35 +540,33 @@ __device__ __forceinline__ void ck_recurse(const Lane<real> &L, const Star<real>
     }
 }
 
-// Per-stage predictor, one launch per derivative order D: reads T^D (or Q for
-// D = 0, which is also copied to T^0) and writes
-// T^{D+1} = dt/(D+1) sum_xi Kt^xi T^D star^xi^T (rows past the staircase 0).
-template <int N, int D, typename real>
-__global__ void __launch_bounds__(64) k_derivative(int64_t E, real dt, const real *__restrict__ Q,
-                                                   const real *__restrict__ star, real *__restrict__ T)
+// Per-stage predictor (Eq. seissol:derivative) in one launch: T^0 = Q is
+// copied while Q streams in, then each order
+// T^{D+1} = dt/(D+1) sum_xi Kt^xi T^D star^xi^T is formed from the previous
+// one held in registers and written as it is formed (rows past the staircase
+// as 0).  Each order reads the same values in the same order as a launch per
+// order reading T^D back from memory would, so T is the same to the bit.
+template <int N, typename real>
+__global__ void __launch_bounds__(64) k_predictor(int64_t E, real dt, const real *__restrict__ Q,
+                                                  const real *__restrict__ star, real *__restrict__ T)
 {
-    constexpr int B = nb3(N), bin = nb3(N - D), bout = nb3(N - D - 1);
+    constexpr int B = nb3(N);
     __shared__ real buf[NCOL * LB<real>];
     const Lane<real> L = make_lane(buf, E, logical_block());
     const Star<real> S = load_star(L, star);
     auto tblk = [&](int g, int d) { return T + (slot_elem(L.base, g, E) * (N + 1) + d) * NQ * B; };
-    real acc[bout];
-#pragma unroll
-    for (int k = 0; k < bout; ++k) acc[k] = real(0);
-    star_contract<N, true, bin>(L, S, acc, [&](auto l0c, auto cntc) {
-        constexpr int l0 = decltype(l0c)::value, cnt = decltype(cntc)::value;
-        if constexpr (D == 0) {
-            chunk_load<cnt, B>(L, [&](int g) -> const real * { return Q + slot_elem(L.base, g, E) * NQ * B; }, l0);
-            lds_sync();
-            chunk_store<cnt, B>(L, [&](int g) { return tblk(g, 0); }, l0, E);
-        } else {
-            chunk_load<cnt, B>(L, [&](int g) -> const real * { return tblk(g, D); }, l0);
-        }
+    auto qblk = [&](int g) -> const real * { return Q + slot_elem(L.base, g, E) * NQ * B; };
+    real q[B];
+    static_for<0, (B + CH<real> - 1) / CH<real>>([&](auto ci) {
+        constexpr int l0 = decltype(ci)::value * CH<real>;
+        constexpr int cnt = (B - l0) < CH<real> ? (B - l0) : CH<real>;
+        chunk_load<cnt, B>(L, qblk, l0);
+        lds_sync();
+        chunk_store<cnt, B>(L, [&](int g) { return tblk(g, 0); }, l0, E);
+        static_for<0, cnt>([&](auto ri) { q[l0 + ri] = L.own[ri]; });
+        lds_sync();
     });
-    const real sc = dt / real(D + 1);
-#pragma unroll
-    for (int k = 0; k < bout; ++k) acc[k] *= sc;
-    store_columns<B, bout, B>(L, [&](int g) { return tblk(g, D + 1); }, acc, E);
+    ck_recurse<N, 0, true, false, false>(L, S, dt, q, static_cast<real *>(nullptr), tblk, E);
 }
 
 // Time integral over stored Taylor-scaled derivatives (FP64 accumulation).

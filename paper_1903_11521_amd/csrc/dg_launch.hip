@@ -35,22 +35,12 @@ struct Launch {
                            (real *)packed);
         return hipGetLastError();
     }
-    template <int D>
-    static hipError_t derivatives(int64_t E, double dt, const void *Q, const void *star, void *T, hipStream_t s)
-    {
-        if constexpr (D < N) {
-            hipLaunchKernelGGL((dgk::k_derivative<N, D, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (real)dt,
-                               (const real *)Q, (const real *)star, (real *)T);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            return derivatives<D + 1>(E, dt, Q, star, T, s);
-        }
-        return hipSuccess;
-    }
     static hipError_t predictor(int64_t E, double dt, const void *Q, const void *star, void *T, hipStream_t s)
     {
         if (E == 0) return hipSuccess;
-        return derivatives<0>(E, dt, Q, star, T, s);
+        hipLaunchKernelGGL((dgk::k_predictor<N, real>), dim3(wave_blocks(E)), dim3(64), 0, s, E, (real)dt,
+                           (const real *)Q, (const real *)star, (real *)T);
+        return hipGetLastError();
     }
     static hipError_t time_integral(int64_t E, double dt, const void *T, void *I, hipStream_t s)
     {
