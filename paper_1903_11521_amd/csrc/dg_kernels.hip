@@ -239,21 +239,51 @@ __device__ __forceinline__ void load_columns(const Lane<real> &L, EPtr eptr, rea
     });
 }
 
-// store this lane's own column rows [0,R) from regs (rows >= RV written as 0)
+// Cooperative store of zeros to rows [l0, l0+CNT) of the columns of the real
+// element slots, in chunk_store's pattern but with no LDS source.
+template <int CNT, int QS, typename real, typename EPtr>
+__device__ __forceinline__ void chunk_zero(const Lane<real> &L, EPtr eptr, int l0, int64_t E)
+{
+    using RS = RowSplit<CNT>;
+    constexpr int K = RS::K;
+    const int g = L.lane >> 3, s = L.lane & 7;
+    if (g < EPW && L.base + g < E) {
+        real *dst = eptr(g) + l0 + s;
+        static_for<0, NQ>([&](auto qi) {
+            static_for<0, K - 1>([&](auto ki) {
+                constexpr int q = decltype(qi)::value, kk = decltype(ki)::value;
+                dst[q * QS + 8 * kk] = real(0);
+            });
+        });
+        if (s < RS::TAIL) {
+            static_for<0, NQ>([&](auto qi) {
+                constexpr int q = decltype(qi)::value;
+                dst[q * QS + 8 * (K - 1)] = real(0);
+            });
+        }
+    }
+}
+
+// store this lane's own column rows [0,R) from regs (rows >= RV written as
+// 0; chunks that hold only such rows are written directly, without LDS)
 template <int R, int RV, int QS, typename real, typename EPtr>
 __device__ __forceinline__ void store_columns(const Lane<real> &L, EPtr eptr, const real *src, int64_t E)
 {
     static_for<0, (R + CH<real> - 1) / CH<real>>([&](auto ci) {
         constexpr int l0 = decltype(ci)::value * CH<real>;
         constexpr int cnt = (R - l0) < CH<real> ? (R - l0) : CH<real>;
-        static_for<0, cnt>([&](auto ri) {
-            constexpr int l = l0 + decltype(ri)::value;
-            if constexpr (l < RV) L.own[ri] = src[l];
-            else L.own[ri] = real(0);
-        });
-        lds_sync();
-        chunk_store<cnt, QS>(L, eptr, l0, E);
-        lds_sync();
+        if constexpr (l0 >= RV) {
+            chunk_zero<cnt, QS>(L, eptr, l0, E);
+        } else {
+            static_for<0, cnt>([&](auto ri) {
+                constexpr int l = l0 + decltype(ri)::value;
+                if constexpr (l < RV) L.own[ri] = src[l];
+                else L.own[ri] = real(0);
+            });
+            lds_sync();
+            chunk_store<cnt, QS>(L, eptr, l0, E);
+            lds_sync();
+        }
     });
 }
 
