@@ -90,6 +90,26 @@ def test_stages(N, E, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("N,E", [(3, 29), (5, 52)])
+def test_time_integral_reads_only_the_staircase(N, E, prec):
+    """dg_time_integral takes the rows of T^d at and past C(N-d+3, 3) as the
+    zeros the predictor leaves there: with those rows filled with noise the
+    result is the oracle's on the staircase-truncated T (stage bar)."""
+    _say(f"test_time_integral_reads_only_the_staircase N={N} E={E} prec={prec}")
+    rng = np.random.default_rng(700 + N)
+    B = refmat.n_basis(N)
+    T = rng.standard_normal((E, N + 1, 9, B))
+    Tz = T.copy()
+    for d in range(N + 1):
+        Tz[:, d, :, refmat.n_basis(N - d):] = 0.0
+    plan = _plan(N, prec)
+    dt = 0.07
+    I = plan.time_integral(_dev(T, plan.dtype), dt)
+    D = Tz / np.array([dt ** k / math.factorial(k) for k in range(N + 1)])[None, :, None, None]
+    assert_close(_host(I), stages.time_integral(N, D, dt), TOL[prec], "time integral")
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_step_config0(prec):
     """One full time step on the 8x8x8x6 = 3072-element jittered periodic mesh,
     degree 3, random materials; element data built by the library itself."""
